@@ -1,0 +1,258 @@
+"""Benchmark of the fused thermal LBM step on one MI355X.
+
+Headline: GLUPS of the FP32 fused step on the 8193 x 8193 D2Q9 + D2Q5
+Rayleigh-Benard cell (Ra 1e8, Pr 0.71), W untimed warm-up steps then K timed
+steps, inputs resident in HBM.  GLUPS = nodes x steps / time / 1e9 (the
+MLUPS definition of Section 2.3, Eq. 10, in units of 1e9).  The same JSON
+line carries the roofline of the step kernel (algorithmic bytes per launch /
+measured launch time against the 8 TB/s HBM peak), the Nu error of the run
+against an FP64 GPU run of the same steps, the 16-bit storage forms and the
+385^3 D3Q19 + D3Q7 cell beside it, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+       [--only NAME] [--no-cpu] [--copy-probe]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+METRIC = "GLUPS & %HBM peak, FP32 vs FP16-store, 8193² D2Q9+D2Q5 / 385³ D3Q19+D3Q7"
+KERNEL_SOURCES = ["paper_2211_03160_amd/csrc/kernels.hpp", "paper_2211_03160_amd/csrc/lattice.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_d2q9_fp32_8193_counters.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed_steps(cav, steps):
+    """Average wall time per step over `steps` launches, measured with HIP
+    events recorded on the stream the kernels are launched on."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(cav.stream)
+    cav.step(steps)
+    e1.record(cav.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms
+
+
+def run_case(cfg, warmup, steps, seed, noise, want_nu=True):
+    import torch
+    from paper_2211_03160_amd import lbm
+    cav = lbm.Cavity(cfg)
+    cav.init(seed, noise)
+    cav.step(warmup)
+    ms = timed_steps(cav, steps)
+    out = {"ms_per_step": ms, "glups": cav.N / (ms * 1e-3) / 1e9,
+           "bytes_per_update": cav.bytes_per_update()}
+    out["hbm_gbs_algorithmic"] = out["glups"] * out["bytes_per_update"]
+    if want_nu:
+        out["nu"] = cav.nusselt()
+        d = cav.diagnostics()
+        out["re"] = d["re"]
+        out["umax"] = d["umax"]
+    del cav
+    torch.cuda.empty_cache()
+    return out
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b) if b else float("nan")
+
+
+def nu_err(nu, ref):
+    return max(rel(nu[0], ref[0]), rel(nu[1], ref[1]))
+
+
+def cpu_baseline(cfg2d, budget_s=12.0):
+    """The FP64 oracle, as it stands, on a strip of the headline cell: the
+    full 8193-node rows, 65 rows high, same walls and parameters; steps run
+    until ~budget_s of wall time."""
+    from oracle.lbmref import Oracle, threads
+    cfg = dict(cfg2d)
+    cfg["n"] = (cfg2d["n"][0], 65, 1)
+    # keep the transport coefficients of the full cell
+    from paper_2211_03160_amd import lbm
+    d = lbm.derive(cfg2d)
+    cfg.update(nu=d["nu"], alpha=d["alpha"], gbeta=d["gbeta"])
+    o = Oracle(cfg)
+    o.init(1234, 1e-3)
+    o.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < 2000:
+        o.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    nodes = cfg["n"][0] * cfg["n"][1]
+    return {"value": nodes * steps / dt / 1e9, "unit": "GLUPS", "cores": threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle on a {cfg['n'][0]}x{cfg['n'][1]} strip of the 8193^2 cell "
+                      f"(same rows, walls and lattice parameters), {steps} steps in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--quick", action="store_true", help="headline only, no variants")
+    ap.add_argument("--only", default=None, help="run a single case by name and exit")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the fused step has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2211_03160_amd import lbm, workloads as W
+    lbm.lib()  # fails loudly if the HIP library is not built
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    c1 = W.C1
+    cfg32 = c1["cfg"]
+    seed, noise = c1["seed"], c1["noise"]
+    K, Wm = args.steps, args.warmup
+
+    cases = {
+        "rb2d_8193_fp32": (cfg32, Wm, K),
+        "rb2d_8193_fp64": (W.with_storage(cfg32, "fp64"), Wm, K),
+        "rb2d_8193_fp16": (W.with_storage(cfg32, "fp16"), Wm, K),
+        "rb2d_8193_bf16": (W.with_storage(cfg32, "bf16"), Wm, K),
+        "rb2d_8193_mixed": (W.with_storage(cfg32, "mixed"), Wm, K),
+        "rb3d_385_fp32": (W.C2["cfg"], 5, W.C2["steps"]),
+        "rb3d_385_fp64": (W.with_storage(W.C2["cfg"], "fp64"), 5, W.C2["steps"]),
+        "rb3d_385_fp16": (W.with_storage(W.C2["cfg"], "fp16"), 5, W.C2["steps"]),
+        "rb3d_385_bf16": (W.with_storage(W.C2["cfg"], "bf16"), 5, W.C2["steps"]),
+        "rb3d_385_mixed": (W.with_storage(W.C2["cfg"], "mixed"), 5, W.C2["steps"]),
+    }
+
+    if args.copy_probe:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 1 GiB device copies done")
+
+    if args.only:
+        cfg, w, k = cases[args.only]
+        r = run_case(cfg, w, k, seed, noise, want_nu=False)
+        log(args.only, json.dumps(r))
+        return
+
+    log(f"headline: 8193^2 D2Q9+D2Q5 FP32, warmup {Wm}, timed {K}")
+    head = run_case(cfg32, Wm, K, seed, noise)
+    log("fp32", json.dumps(head))
+    ref64 = run_case(cases["rb2d_8193_fp64"][0], Wm, K, seed, noise)
+    log("fp64", json.dumps(ref64))
+
+    N = cfg32["n"][0] * cfg32["n"][1]
+    bpu = head["bytes_per_update"]
+    launch_s = head["ms_per_step"] * 1e-3
+    achieved = N * bpu / launch_s / 1e9
+    traffic = read_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic,
+                "kernel": "lbm::step_kernel<2, StF32>",
+                "bytes_per_lattice_update": bpu}
+
+    variants = {"rb2d_8193_fp64": {**ref64}}
+    if not args.quick:
+        for name in ("rb2d_8193_fp16", "rb2d_8193_bf16", "rb2d_8193_mixed"):
+            cfg, w, k = cases[name]
+            r = run_case(cfg, w, k, seed, noise)
+            r["nu_rel_err_vs_fp64"] = nu_err(r["nu"], ref64["nu"])
+            variants[name] = r
+            log(name, json.dumps(r))
+        ref3 = run_case(cases["rb3d_385_fp64"][0], 5, W.C2["steps"], W.C2["seed"], W.C2["noise"])
+        variants["rb3d_385_fp64"] = ref3
+        log("rb3d_385_fp64", json.dumps(ref3))
+        for name in ("rb3d_385_fp32", "rb3d_385_fp16", "rb3d_385_bf16", "rb3d_385_mixed"):
+            cfg, w, k = cases[name]
+            r = run_case(cfg, w, k, W.C2["seed"], W.C2["noise"])
+            r["nu_rel_err_vs_fp64"] = nu_err(r["nu"], ref3["nu"])
+            r["re_rel_err_vs_fp64"] = rel(r["re"], ref3["re"])
+            r["hbm_frac"] = r["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
+            variants[name] = r
+            log(name, json.dumps(r))
+
+    cpu = None if args.no_cpu else cpu_baseline(cfg32)
+    if cpu:
+        log("cpu baseline", json.dumps(cpu))
+
+    for v in variants.values():
+        for k in list(v):
+            if isinstance(v[k], float):
+                v[k] = float(f"{v[k]:.6g}")
+    line = {
+        "metric": METRIC,
+        "value": round(head["glups"], 3),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rb2d_8193x8193_d2q9_d2q5_ra1e8_pr0.71_fp32",
+                   "grid": [8193, 8193], "lattice": "D2Q9+D2Q5", "storage": "fp32",
+                   "ra": 1e8, "pr": 0.71, "seed": seed, "noise": noise},
+        "nu": head["nu"],
+        "nu_rel_err_vs_fp64": float(f"{nu_err(head['nu'], ref64['nu']):.3g}"),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "context": {"paper_single_gpu_glups": {"2d_8193": 1.9312, "3d_385": 1.0424},
+                    "paper_hardware": "NVIDIA A100 1555 GB/s, FP64, side-heated cavity"},
+        "kernel_source_sha256": kernel_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) thermal lattice Boltzmann library.
+ *
+ * The library advances the double-distribution-function (DDF) thermal
+ * lattice Boltzmann model of Xu & Li, "Multi-GPU thermal lattice Boltzmann
+ * simulations using OpenACC and MPI" (arXiv:2211.03160), Section 2:
+ *   - flow populations f on D2Q9 (3D: D3Q19) with the multiple-relaxation-
+ *     time collision of Eq. (5) / Eq. (8a) and the Guo forcing of
+ *     Eqs. (6a)/(6b), driven by the Boussinesq buoyancy force
+ *     F = rho g beta (T - T0) along the upward axis (Section 2.2);
+ *   - temperature populations g on D2Q5 (3D: D3Q7) with the MRT collision
+ *     of Eq. (7) / Eq. (9a);
+ *   - half-way bounce-back on no-slip walls, half-way anti-bounce-back on
+ *     isothermal (Dirichlet) walls and bounce-back of g on adiabatic walls
+ *     (Section 2.2), or periodic faces.
+ * One time step is ONE fused GPU kernel: pull-streaming (Eqs. 8b, 9b) with
+ * the wall rules, the moments, both collisions and the store of the
+ * post-collision populations.
+ *
+ * Conventions
+ *   - Every function returns an lbm_status (or a documented value); none
+ *     throws, aborts or exits.  On failure lbm_last_error() describes it.
+ *   - The library NEVER allocates device memory.  The caller provides one
+ *     device workspace of lbm_workspace_bytes() bytes (e.g. a uint8 tensor)
+ *     and a HIP stream; both must outlive the context.  Host memory of the
+ *     context itself is owned by the library and freed by lbm_destroy().
+ *   - All kernels run on the caller's stream, in stream order.  lbm_step()
+ *     only enqueues; lbm_fields/lbm_nusselt/lbm_diagnostics/lbm_wall_flux/
+ *     lbm_export_state synchronise the stream before returning.
+ *   - A context is used by one host thread at a time.
+ *   - Node (x, y, z) has flat index x + nx*(y + ny*z) (x fastest), the
+ *     structure-of-arrays order of Section 3.1.  Faces are ordered
+ *     -x, +x, -y, +y, -z, +z.  Gravity points along -y (2D) or -z (3D).
+ *   - Field arrays: rho[N], T[N], u[dim][N] (component-major), FP64.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_E_INVALID (-1)     /* bad argument or parameter                */
+#define LBM_E_DEVICE (-2)      /* a HIP call failed                        */
+#define LBM_E_UNSTABLE (-3)    /* non-finite populations at a sync point   */
+#define LBM_E_STATE (-4)       /* call out of order                        */
+#define LBM_E_UNSUPPORTED (-5) /* valid request this build cannot serve    */
+
+/* Population storage.  Collision arithmetic is FP32 for every mode except
+ * LBM_FP64, which computes in FP64 (the accuracy reference).  The 16-bit
+ * modes store f_i - w_i and g_i - w_i^T T0 (w_i^T: rest-state weights of
+ * the thermal equilibrium), rounded to nearest even.                    */
+#define LBM_FP32 0
+#define LBM_FP64 1
+#define LBM_FP16_SHIFTED 2
+#define LBM_BF16_SHIFTED 3
+#define LBM_MIXED_F16_G32 4 /* f as shifted FP16, g as FP32 */
+
+/* Boundary kind per face */
+#define LBM_BC_PERIODIC 0  /* both faces of an axis, or neither       */
+#define LBM_BC_ADIABATIC 1 /* no-slip wall, zero heat flux             */
+#define LBM_BC_DIRICHLET 2 /* no-slip wall at temperature t_wall[face] */
+
+/* Run parameters, copied by lbm_create.  Any double documented as
+ * "NaN: default" takes the default when set to NaN.                    */
+typedef struct lbm_params {
+    int32_t dim;      /* 2 (D2Q9 + D2Q5) or 3 (D3Q19 + D3Q7)               */
+    int32_t n[3];     /* nodes along x, y, z; n[2] == 1 when dim == 2      */
+    int32_t storage;  /* LBM_FP32 ... LBM_MIXED_F16_G32                    */
+    int32_t bc[6];    /* LBM_BC_* per face                                 */
+    int32_t reserved; /* must be 0                                         */
+    double t_wall[6]; /* temperature of each DIRICHLET face                */
+    double ra, pr;    /* Rayleigh and Prandtl numbers, Eq. (4)             */
+    double u_ff;      /* free-fall velocity sqrt(g beta dT H), lattice units */
+    double t_hot, t_cold; /* dT = t_hot - t_cold, T0 = (t_hot + t_cold)/2  */
+    /* Transport coefficients in lattice units.  NaN: from Eqs. (2)-(4)
+     * with H = n along gravity: nu = u_ff H sqrt(Pr/Ra),
+     * alpha = u_ff H / sqrt(Pr Ra), g beta = u_ff^2 / (dT H).            */
+    double nu, alpha, gbeta;
+    double a_t; /* thermal-equilibrium constant a_T; NaN: -1.5 (2D), -0.75 (3D) */
+    /* Flow MRT rates of the non-conserved moments; the shear rate is
+     * s_nu = 1/(3 nu + 1/2).  NaN: s_e = s_eps = s_pi = s_nu and
+     * s_q = s_m = 8 (2 - s_nu) / (8 - s_nu).                              */
+    double s_e, s_eps, s_q, s_pi, s_m;
+    /* Thermal MRT rates of the even non-conserved moments (NaN: 1); the
+     * flux rate is q_j = 1/(alpha/c_sT^2 + 1/2), c_sT^2 = 2 w^T_moving.   */
+    double q_e, q_nu;
+} lbm_params;
+
+typedef struct lbm_diag {
+    int64_t t;         /* time step of the state                          */
+    double mass;       /* sum over nodes of rho                           */
+    double energy;     /* sum over nodes of T                             */
+    double umax;       /* max over nodes of |u|                           */
+    double nu_vol;     /* 1 + H <u_g (T - T0)> / (alpha dT), u_g upward   */
+    double re;         /* sqrt(<|u|^2>) H / nu                            */
+    int64_t nonfinite; /* number of non-finite stored populations         */
+} lbm_diag;
+
+/* Derived parameters returned by lbm_derive, in this order. */
+#define LBM_D_NU 0
+#define LBM_D_ALPHA 1
+#define LBM_D_GBETA 2
+#define LBM_D_TAU_F 3
+#define LBM_D_TAU_G 4
+#define LBM_D_S_NU 5
+#define LBM_D_S_E 6
+#define LBM_D_S_EPS 7
+#define LBM_D_S_Q 8
+#define LBM_D_S_PI 9
+#define LBM_D_S_M 10
+#define LBM_D_Q_J 11
+#define LBM_D_Q_E 12
+#define LBM_D_Q_NU 13
+#define LBM_D_A_T 14
+#define LBM_D_OMEGA 15 /* anti-bounce-back weight, Section 2.2 */
+#define LBM_D_CS2_T 16
+#define LBM_D_T0 17
+#define LBM_D_H 18
+#define LBM_D_COUNT 19
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Host only (no GPU needed).  Validates *p and fills out[LBM_D_COUNT]
+ * (out may be NULL).  Returns LBM_E_INVALID with a message in
+ * lbm_last_error(NULL) when the parameters are rejected: dim not 2/3,
+ * n < 1, unpaired periodic faces, a walled axis with n < 2, more than
+ * 2^31 - 1 nodes, non-positive nu/alpha, relaxation rates outside (0, 2)
+ * (tau_f or tau_g <= 1/2), a_t outside (-4, 1) in 2D / (-6, 1) in 3D,
+ * unknown storage.                                                       */
+lbm_status lbm_derive(const lbm_params* p, double* out);
+
+/* Host only.  Device workspace bytes needed for *p; 0 if *p is invalid. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Bytes moved to/from HBM per lattice update by the step kernel in its
+ * algorithmic minimum (each population read once and written once).    */
+double lbm_bytes_per_update(const lbm_params* p);
+
+/* Creates a context on the current HIP device.  d_workspace: device
+ * pointer, 256-byte aligned, at least lbm_workspace_bytes(p) bytes, owned
+ * by the caller.  hip_stream: a hipStream_t (NULL = default stream).
+ * The state is undefined until lbm_init or lbm_init_fields.             */
+lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t bytes,
+                      void* hip_stream, lbm_ctx** out);
+
+/* Resting start: rho = 1, u = 0, T = linear conduction profile between
+ * the two Dirichlet faces of one axis (the gravity axis first; T0 when
+ * there is none) plus amp * xi, xi in [-1, 1) drawn per node from
+ * SplitMix64: xi = 2 * (s(seed ^ s(idx)) >> 11) * 2^-53 - 1, with s() one
+ * SplitMix64 step from the given state and idx the flat node index.
+ * Populations start at their equilibria.  Sets t = 0.  Asynchronous.   */
+lbm_status lbm_init(lbm_ctx* c, uint64_t seed, double amp);
+
+/* Start from host fields: populations at the equilibria of (rho, u, T).
+ * rho may be NULL (rho = 1); u is [dim][N]; T is [N].  Sets t = 0.
+ * Copies through the workspace staging area; returns after the copies.  */
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
+                           const double* T);
+
+/* Enqueues n fused steps (n = 0: no-op; n < 0: LBM_E_INVALID).          */
+lbm_status lbm_step(lbm_ctx* c, int64_t n);
+
+/* Moments of the current state at time t (the pre-collision moments
+ * rho = sum f, u = (sum e f + F/2)/rho, T = sum g of Section 2.2),
+ * computed in FP64 from the stored populations.  Each pointer may be
+ * NULL, host or device memory.  Synchronises.  LBM_E_UNSTABLE (after
+ * writing the outputs) if any stored population is non-finite.          */
+lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T);
+
+/* Wall Nusselt numbers, FP64, averaged over the last two steps.  The heat
+ * entering through a Dirichlet wall link per step is omega T_w - 2 g_out+
+ * (anti-bounce-back, Section 2.2); Nu = L q / (alpha dT) with q the heat
+ * flux per unit wall area and L the node count across that axis.  Hot
+ * faces are Dirichlet faces warmer than T0, cold faces colder (their
+ * outgoing flux is counted positive).  LBM_E_STATE if t < 2 or a hot or
+ * cold face is missing; LBM_E_UNSTABLE (after writing the outputs) if a
+ * result is not finite.  Synchronises.                                  */
+lbm_status lbm_nusselt(lbm_ctx* c, double* nu_hot, double* nu_cold);
+
+/* Heat entering through each face during the last step (last[6]) and the
+ * step before (prev[6]); zero for non-Dirichlet faces.  Synchronises.   */
+lbm_status lbm_wall_flux(lbm_ctx* c, double* last, double* prev);
+
+/* FP64 reductions over all nodes.  Synchronises.                        */
+lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* d);
+
+/* Checkpoint: the stored populations, the wall-flux history and t.
+ * lbm_state_bytes gives the size; export writes it to host memory and
+ * synchronises; import reads a buffer exported by a context with the same
+ * parameters.                                                           */
+size_t lbm_state_bytes(const lbm_ctx* c);
+lbm_status lbm_export_state(lbm_ctx* c, void* host, size_t bytes);
+lbm_status lbm_import_state(lbm_ctx* c, const void* host, size_t bytes);
+
+int64_t lbm_time(const lbm_ctx* c); /* -1 before init, -1 for NULL */
+void lbm_destroy(lbm_ctx* c);       /* NULL-safe; does not synchronise    */
+
+/* Last error of a context, or of lbm_derive/lbm_workspace_bytes/
+ * lbm_create on this thread when c is NULL.  Never NULL.                */
+const char* lbm_last_error(const lbm_ctx* c);
+
+/* Host only.  The tables the kernels are compiled with.  which: 0 flow,
+ * 1 thermal.  q: lattice size; e[q*3] velocities; M[q*q] moment basis
+ * (row = moment, integer entries); w[q] flow weights (which = 0) or
+ * rest-state thermal weights for a_T = default (which = 1).  Any output
+ * may be NULL.                                                          */
+lbm_status lbm_lattice(int32_t dim, int32_t which, int32_t* q, int32_t* e,
+                       int32_t* M, double* w);
+
+/* Host only.  Version string of the library build.                      */
+const char* lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

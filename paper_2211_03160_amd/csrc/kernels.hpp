@@ -1,0 +1,620 @@
+// kernels.hpp -- gfx950 kernels of the fused DDF thermal LBM step.
+//
+// One launch of step_kernel advances every node by one time step of the
+// model of Section 2.2 (Eqs. 5-7) in the collide/stream split of Section
+// 3.1 (Eqs. 8a-9b), fused into a single pass:
+//   pull: f_i(x) = f+_i(x - e_i) and g_i(x) = g+_i(x - e_i) from buffer A,
+//         with half-way bounce-back / anti-bounce-back where x - e_i lies
+//         beyond a wall (Section 2.2) and wrap-around on periodic faces;
+//   moments: rho, T, buoyancy F = rho g beta (T - T0) e_up, u = (j + F/2)/rho;
+//   collide f in moment space with Guo forcing (Eqs. 5, 6a/6b, 8a);
+//   collide g in moment space (Eqs. 7, 9a);
+//   store f+, g+ at x into buffer B.
+// A and B hold POST-collision populations in structure-of-arrays order
+// (one plane of N values per velocity, x fastest; Section 3.1).
+//
+// Arithmetic is carried out on deviations h_i = f_i - w_i (flow) and
+// h^g_i = g_i - w^T_i T_b (thermal, T_b = T0 for 16-bit storage, else 0),
+// so moments of order one never swamp the small non-equilibrium parts.
+// With orthogonal bases the collision is applied as an increment:
+//   h+_i = h_i + sum_k M_ki dm_k / |M_k|^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+constexpr int kBlock = 256;  // threads per block of the node-parallel kernels
+constexpr int kXcd = 8;      // accelerator complex dies of an MI355X
+
+// ------------------------------------------------------------------ storage
+// Element codecs: stored type T, dec() to the compute type, enc() from it.
+// The 16-bit codecs round to nearest even.
+struct E32 {
+    using T = float;
+    __device__ static float dec(T v) { return v; }
+    __device__ static T enc(float v) { return v; }
+};
+struct E64 {
+    using T = double;
+    __device__ static double dec(T v) { return v; }
+    __device__ static T enc(double v) { return v; }
+};
+struct E16 {
+    using T = _Float16;
+    __device__ static float dec(T v) { return (float)v; }
+    __device__ static T enc(float v) { return (T)v; }
+};
+struct EB16 {  // bfloat16 kept as raw bits
+    using T = uint16_t;
+    __device__ static float dec(T v) { return __uint_as_float((uint32_t)v << 16); }
+    __device__ static T enc(float v) {
+        const uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
+        return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    }
+};
+
+// A storage mode: codecs of f and g, compute type R, and whether the stored
+// value is the deviation itself (16-bit codecs) or the population.
+template <class CF, class CG, class Real> struct Storage {
+    using EF = CF;
+    using EG = CG;
+    using TF = typename CF::T;
+    using TG = typename CG::T;
+    using R = Real;
+    static constexpr bool f_dev = sizeof(TF) == 2;
+    static constexpr bool g_dev = sizeof(TG) == 2;
+};
+using StF32 = Storage<E32, E32, float>;
+using StF64 = Storage<E64, E64, double>;
+using StF16 = Storage<E16, E16, float>;
+using StBF16 = Storage<EB16, EB16, float>;
+using StMix = Storage<E16, E32, float>;
+
+// --------------------------------------------------------------- parameters
+// x / d for x < 2^31 by multiply-high (round-up method of Granlund and
+// Montgomery, 1994): q = (umulhi(x, m) + x) >> l, l = ceil(log2 d).
+struct FastDiv {
+    uint32_t d, m, l;
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t x) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+        return (__umulhi(x, m) + x) >> l;
+#else
+        return (uint32_t)((((uint64_t)x * m) >> 32) + x) >> l;
+#endif
+    }
+};
+
+struct Geometry {
+    uint32_t N, nx, ny, nz;
+    FastDiv divx, divy;
+    int32_t periodic[3];
+    int32_t dirichlet[6];
+    uint32_t blocks_per_xcd;  // logical blocks handled by each XCD
+};
+
+template <class R> struct Coef {
+    R s[19];     // flow rate per moment row (0 on conserved rows)
+    R b[19];     // 1 - s/2 per row
+    R q[7];      // thermal rate per row
+    R a_t;       // thermal equilibrium constant a_T
+    R gbeta;     // g beta
+    R t_base;    // T_b
+    R tb_m_t0;   // T_b - T0
+    R abb[6];    // omega (T_w - T_b) on Dirichlet faces
+    double abb_d[6];  // the same in FP64, for the wall heat flux
+};
+
+template <class St> struct StepArgs {
+    const typename St::TF* fsrc;
+    const typename St::TG* gsrc;
+    typename St::TF* fdst;
+    typename St::TG* gdst;
+    double* flux[6];  // per-node wall heat flux of this step, per face
+    Geometry geo;
+    Coef<typename St::R> c;
+};
+
+// logical block id: blocks are dealt to the XCDs round-robin, so give each
+// XCD a contiguous run of the domain (its L2 then holds the lines shared
+// between neighbouring blocks)
+__device__ __forceinline__ uint32_t logical_block(uint32_t per_xcd) {
+    const uint32_t b = blockIdx.x;
+    return (b % kXcd) * per_xcd + b / kXcd;
+}
+
+__device__ __forceinline__ void coords(const Geometry& g, uint32_t idx, uint32_t& x,
+                                       uint32_t& y, uint32_t& z) {
+    const uint32_t r = g.divx.div(idx);
+    x = idx - r * g.nx;
+    z = g.divy.div(r);
+    y = r - z * g.ny;
+}
+
+// -------------------------------------------------------------- arithmetic
+// compile-time loop: f(std::integral_constant<int, B>), ..., up to E - 1
+template <int B, int E, class F> __device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// acc += C v for a compile-time integer coefficient C
+template <int C, class R> __device__ __forceinline__ void cmac(R& acc, R v) {
+    if constexpr (C == 1) acc += v;
+    else if constexpr (C == -1) acc -= v;
+    else if constexpr (C != 0) acc += R(C) * v;
+}
+
+// m_eq(rho, u) - m_eq(1, 0) for the non-conserved rows (second-order
+// equilibrium with local rho)
+template <int DIM, class R>
+__device__ __forceinline__ R eq_dev(int k, R rho, R drho, const R* u) {
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if constexpr (DIM == 2) {
+        switch (k) {
+        case 1: return R(-2) * drho + R(3) * rho * uu;
+        case 2: return drho - R(3) * rho * uu;
+        case 4: return -rho * u[0];
+        case 6: return -rho * u[1];
+        case 7: return rho * (u[0] * u[0] - u[1] * u[1]);
+        case 8: return rho * u[0] * u[1];
+        default: return R(0);
+        }
+    } else {
+        const R pxx = R(3) * u[0] * u[0] - uu, pww = u[1] * u[1] - u[2] * u[2];
+        switch (k) {
+        case 1: return R(-11) * drho + R(19) * rho * uu;
+        case 2: return R(3) * drho - R(5.5) * rho * uu;
+        case 4: return R(-2.0 / 3.0) * rho * u[0];
+        case 6: return R(-2.0 / 3.0) * rho * u[1];
+        case 8: return R(-2.0 / 3.0) * rho * u[2];
+        case 9: return rho * pxx;
+        case 10: return R(-0.5) * rho * pxx;
+        case 11: return rho * pww;
+        case 12: return R(-0.5) * rho * pww;
+        case 13: return rho * u[0] * u[1];
+        case 14: return rho * u[1] * u[2];
+        case 15: return rho * u[0] * u[2];
+        default: return R(0);
+        }
+    }
+}
+
+// forcing moments M F~ of Eq. (6a) / Eq. (6b); the xy entry of Eq. (6a)
+// is u F_y + v F_x
+template <int DIM, class R>
+__device__ __forceinline__ R force_mom(int k, const R* u, const R* F) {
+    const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    if constexpr (DIM == 2) {
+        switch (k) {
+        case 1: return R(6) * uF;
+        case 2: return R(-6) * uF;
+        case 4: return -F[0];
+        case 6: return -F[1];
+        case 7: return R(2) * u[0] * F[0] - R(2) * u[1] * F[1];
+        case 8: return u[0] * F[1] + u[1] * F[0];
+        default: return R(0);
+        }
+    } else {
+        switch (k) {
+        case 1: return R(38) * uF;
+        case 2: return R(-11) * uF;
+        case 4: return R(-2.0 / 3.0) * F[0];
+        case 6: return R(-2.0 / 3.0) * F[1];
+        case 8: return R(-2.0 / 3.0) * F[2];
+        case 9: return R(4) * u[0] * F[0] - R(2) * u[1] * F[1] - R(2) * u[2] * F[2];
+        case 10: return R(-2) * u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+        case 11: return R(2) * u[1] * F[1] - R(2) * u[2] * F[2];
+        case 12: return -u[1] * F[1] + u[2] * F[2];
+        case 13: return u[0] * F[1] + u[1] * F[0];
+        case 14: return u[1] * F[2] + u[2] * F[1];
+        case 15: return u[0] * F[2] + u[2] * F[0];
+        default: return R(0);
+        }
+    }
+}
+
+// Moments, both collisions and the store of one node.  hf/hg hold the
+// pre-collision deviations on entry.
+template <int DIM, class St>
+__device__ __forceinline__ void collide_store(typename St::R* hf, typename St::R* hg,
+                                              const Coef<typename St::R>& c,
+                                              typename St::TF* __restrict__ fdst,
+                                              typename St::TG* __restrict__ gdst, uint32_t N,
+                                              uint32_t idx) {
+    using R = typename St::R;
+    using L = Flow<DIM>;
+    using H = Heat<DIM>;
+    constexpr int QF = L::Q, QG = H::Q;
+
+    R drho = R(0), j[3] = {R(0), R(0), R(0)}, dT = R(0);
+    static_for<0, QF>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        drho += hf[i];
+        cmac<L::ex[i]>(j[0], hf[i]);
+        cmac<L::ey[i]>(j[1], hf[i]);
+        cmac<L::ez[i]>(j[2], hf[i]);
+    });
+    static_for<0, QG>([&](auto ic) { dT += hg[decltype(ic)::value]; });
+    const R rho = R(1) + drho;
+    const R T = c.t_base + dT;
+    R F[3] = {R(0), R(0), R(0)};
+    F[DIM - 1] = rho * c.gbeta * (dT + c.tb_m_t0);  // buoyancy, upward
+    const R inv_rho = R(1) / rho;
+    R u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + R(0.5) * F[a]) * inv_rho;
+
+    // flow: dm_k for every row, scaled by 1/|M_k|^2
+    R dm[QF];
+    static_for<0, QF>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int kind = L::kind[k];
+        R d;
+        if constexpr (kind == kRho) {
+            d = R(0);
+        } else if constexpr (kind == kJx || kind == kJy || kind == kJz) {
+            d = F[kind - kJx];  // momentum gains exactly F for any rate
+        } else {
+            R mk = R(0);
+            static_for<0, QF>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                cmac<L::M(k, i)>(mk, hf[i]);
+            });
+            d = -c.s[k] * (mk - eq_dev<DIM>(k, rho, drho, u)) + c.b[k] * force_mom<DIM>(k, u, F);
+        }
+        dm[k] = d * R(1.0 / row_norm<L>(k));
+    });
+    static_for<0, QF>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        R acc = hf[i];
+        static_for<1, QF>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            cmac<L::M(k, i)>(acc, dm[k]);
+        });
+        hf[i] = acc;
+    });
+
+    // thermal: n_eq = (T, u T, a_T T, 0...) in deviation form
+    R dn[QG];
+    static_for<0, QG>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int kind = H::kind[k];
+        R nk = R(0);
+        static_for<0, QG>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            cmac<H::M(k, i)>(nk, hg[i]);
+        });
+        R d;
+        if constexpr (kind == kRho) d = R(0);
+        else if constexpr (kind == kJx || kind == kJy || kind == kJz) d = -c.q[k] * (nk - u[kind - kJx] * T);
+        else if constexpr (kind == kE) d = -c.q[k] * (nk - c.a_t * dT);
+        else d = -c.q[k] * nk;
+        dn[k] = d * R(1.0 / row_norm<H>(k));
+    });
+    static_for<0, QG>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        R acc = hg[i];
+        static_for<1, QG>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            cmac<H::M(k, i)>(acc, dn[k]);
+        });
+        hg[i] = acc;
+    });
+
+    // store post-collision populations at the node
+    static_for<0, QF>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const R v = St::f_dev ? hf[i] : R(L::w[i]) + hf[i];
+        __builtin_nontemporal_store(St::EF::enc(v), fdst + (size_t)i * N + idx);
+    });
+    static_for<0, QG>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        __builtin_nontemporal_store(St::EG::enc(hg[i]), gdst + (size_t)i * N + idx);
+    });
+}
+
+// ----------------------------------------------------------------- the step
+template <int DIM, class St>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
+    using R = typename St::R;
+    using TF = typename St::TF;
+    using TG = typename St::TG;
+    using L = Flow<DIM>;
+    using H = Heat<DIM>;
+    const Geometry& g = a.geo;
+    const uint32_t idx = logical_block(g.blocks_per_xcd) * kBlock + threadIdx.x;
+    if (idx >= g.N) return;
+    uint32_t x, y, z;
+    coords(g, idx, x, y, z);
+
+    // pull offsets along each axis: a velocity with e_a = +1 pulls from
+    // coordinate c - 1 ("m"), e_a = -1 from c + 1 ("p")
+    const int32_t nx = (int32_t)g.nx, sy = nx, sz = nx * (int32_t)g.ny;
+    const bool inxm = x > 0, inxp = x + 1 < g.nx;
+    const bool inym = y > 0, inyp = y + 1 < g.ny;
+    const bool inzm = z > 0, inzp = z + 1 < g.nz;
+    const bool okxm = inxm || g.periodic[0], okxp = inxp || g.periodic[0];
+    const bool okym = inym || g.periodic[1], okyp = inyp || g.periodic[1];
+    const bool okzm = inzm || g.periodic[2], okzp = inzp || g.periodic[2];
+    const int32_t oxm = inxm ? -1 : nx - 1, oxp = inxp ? 1 : 1 - nx;
+    const int32_t oym = inym ? -sy : ((int32_t)g.ny - 1) * sy;
+    const int32_t oyp = inyp ? sy : -((int32_t)g.ny - 1) * sy;
+    const int32_t ozm = inzm ? -sz : ((int32_t)g.nz - 1) * sz;
+    const int32_t ozp = inzp ? sz : -((int32_t)g.nz - 1) * sz;
+    const uint32_t N = g.N;
+
+    R hf[L::Q], hg[H::Q];
+    static_for<0, L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
+        const bool out = (ex > 0 && !okxm) || (ex < 0 && !okxp) || (ey > 0 && !okym) ||
+                         (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
+        const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
+                            (ez > 0 ? ozm : ez < 0 ? ozp : 0);
+        const TF* plane = a.fsrc + (size_t)i * N;
+        TF v = plane[out ? idx : (uint32_t)((int32_t)idx + off)];
+        if (out) v = a.fsrc[(size_t)L::opp[i] * N + idx];  // half-way bounce-back
+        const R r = St::EF::dec(v);
+        hf[i] = St::f_dev ? r : r - R(L::w[i]);
+    });
+    static_for<0, H::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ex = H::ex[i], ey = H::ey[i], ez = H::ez[i];
+        const bool out = (ex > 0 && !okxm) || (ex < 0 && !okxp) || (ey > 0 && !okym) ||
+                         (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
+        const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
+                            (ez > 0 ? ozm : ez < 0 ? ozp : 0);
+        const TG* plane = a.gsrc + (size_t)i * N;
+        R r = St::EG::dec(plane[out ? idx : (uint32_t)((int32_t)idx + off)]);
+        if (out) {
+            // the wall this link crosses: axis of e_i, the side it comes from
+            constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
+            constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
+            const R back = St::EG::dec(a.gsrc[(size_t)H::opp[i] * N + idx]);
+            if (g.dirichlet[face]) {
+                r = a.c.abb[face] - back;  // anti-bounce-back
+                const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
+                a.flux[face][local] = a.c.abb_d[face] - 2.0 * (double)back;
+            } else {
+                r = back;  // adiabatic bounce-back
+            }
+        }
+        hg[i] = r;
+    });
+    collide_store<DIM, St>(hf, hg, a.c, a.fdst, a.gdst, N, idx);
+}
+
+// -------------------------------------------------------------- init kernel
+template <class St> struct InitArgs {
+    typename St::TF* fdst;
+    typename St::TG* gdst;
+    Geometry geo;
+    Coef<typename St::R> c;
+    uint32_t n0, cnt;  // node range of this launch
+    int32_t mode;      // 0: profile + noise, 1: fields from device arrays
+    int32_t axis;      // conduction axis (-1: uniform T0)
+    double t_lo, t_hi, t0;
+    double amp;
+    uint64_t seed;
+    const double* rho;  // mode 1: [cnt] or null
+    const double* u;    // mode 1: [DIM][cnt]
+    const double* T;    // mode 1: [cnt]
+    double w_rest, w_move;  // thermal rest-state weights
+};
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <int DIM, class St>
+__global__ __launch_bounds__(kBlock) void init_kernel(InitArgs<St> a) {
+    using R = typename St::R;
+    using L = Flow<DIM>;
+    using H = Heat<DIM>;
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= a.cnt) return;
+    const uint32_t idx = a.n0 + k;
+    uint32_t x, y, z;
+    coords(a.geo, idx, x, y, z);
+    double rho = 1.0, T, u[3] = {0.0, 0.0, 0.0};
+    if (a.mode == 0) {
+        const uint32_t cx[3] = {x, y, z};
+        const double na = a.axis == 0 ? a.geo.nx : a.axis == 1 ? a.geo.ny : a.geo.nz;
+        T = a.axis >= 0 ? a.t_lo + ((double)cx[a.axis] + 0.5) * (a.t_hi - a.t_lo) / na : a.t0;
+        const uint64_t r = splitmix64(a.seed ^ splitmix64((uint64_t)idx));
+        T += a.amp * (2.0 * ((double)(r >> 11) * 0x1.0p-53) - 1.0);
+    } else {
+        if (a.rho) rho = a.rho[k];
+        for (int d = 0; d < DIM; ++d) u[d] = a.u[(size_t)d * a.cnt + k];
+        T = a.T[k];
+    }
+    // equilibria as deviations: f_eq - w = w (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu)),
+    // g_eq - w^T T_b = w^T (T - T_b) + (e.u) T / 2
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    R hf[L::Q], hg[H::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double eu = L::ex[i] * u[0] + L::ey[i] * u[1] + L::ez[i] * u[2];
+        hf[i] = (R)(L::w[i] * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
+    }
+    const double tb = (double)a.c.t_base;
+#pragma unroll
+    for (int i = 0; i < H::Q; ++i) {
+        const double eu = H::ex[i] * u[0] + H::ey[i] * u[1] + H::ez[i] * u[2];
+        const double wt = i == 0 ? a.w_rest : a.w_move;
+        hg[i] = (R)(wt * (T - tb) + 0.5 * eu * T);
+    }
+    collide_store<DIM, St>(hf, hg, a.c, a.fdst, a.gdst, a.geo.N, idx);
+}
+
+// ----------------------------------------------------- moments of one node
+// FP64 moments of the stored post-collision populations at node idx:
+// rho = sum f+, T = sum g+, j+ = sum e f+ = j + F, so u = (j+ - F/2)/rho.
+template <int DIM, class St> struct NodeMoments {
+    double rho, T, u[3];
+    int nonfinite;
+};
+
+template <int DIM, class St>
+__device__ __forceinline__ NodeMoments<DIM, St> node_moments(const typename St::TF* fsrc,
+                                                             const typename St::TG* gsrc,
+                                                             uint32_t N, uint32_t idx,
+                                                             double gbeta, double t_base,
+                                                             double t0) {
+    using L = Flow<DIM>;
+    using H = Heat<DIM>;
+    NodeMoments<DIM, St> m;
+    double drho = 0.0, j[3] = {0.0, 0.0, 0.0}, dT = 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double v = (double)St::EF::dec(fsrc[(size_t)i * N + idx]);
+        const double h = St::f_dev ? v : v - L::w[i];
+        bad += !isfinite(h);
+        drho += h;
+        j[0] += L::ex[i] * h;
+        j[1] += L::ey[i] * h;
+        j[2] += L::ez[i] * h;
+    }
+#pragma unroll
+    for (int i = 0; i < H::Q; ++i) {
+        const double h = (double)St::EG::dec(gsrc[(size_t)i * N + idx]);
+        bad += !isfinite(h);
+        dT += h;
+    }
+    m.rho = 1.0 + drho;
+    m.T = t_base + dT;
+    double F[3] = {0.0, 0.0, 0.0};
+    F[DIM - 1] = m.rho * gbeta * (m.T - t0);
+    for (int a = 0; a < 3; ++a) m.u[a] = (j[a] - 0.5 * F[a]) / m.rho;
+    m.nonfinite = bad;
+    return m;
+}
+
+template <class St> struct FieldArgs {
+    const typename St::TF* fsrc;
+    const typename St::TG* gsrc;
+    uint32_t N, n0, cnt;
+    double gbeta, t_base, t0;
+    double* rho;  // [cnt] or null
+    double* u;    // [DIM][cnt] or null
+    double* T;    // [cnt] or null
+    unsigned long long* nonfinite;  // atomic counter
+};
+
+template <int DIM, class St>
+__global__ __launch_bounds__(kBlock) void fields_kernel(FieldArgs<St> a) {
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= a.cnt) return;
+    const auto m = node_moments<DIM, St>(a.fsrc, a.gsrc, a.N, a.n0 + k, a.gbeta, a.t_base, a.t0);
+    if (a.rho) a.rho[k] = m.rho;
+    if (a.T) a.T[k] = m.T;
+    if (a.u)
+        for (int d = 0; d < DIM; ++d) a.u[(size_t)d * a.cnt + k] = m.u[d];
+    if (m.nonfinite) atomicAdd(a.nonfinite, (unsigned long long)m.nonfinite);
+}
+
+// ---------------------------------------------------------------- reductions
+// 64-wide wavefront shuffle, then LDS across the block's waves.
+template <class Op> __device__ __forceinline__ double wave_reduce(double v, Op op) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+template <int NT, class Op>
+__device__ __forceinline__ double block_reduce(double v, Op op, double* lds) {
+    constexpr int W = NT / 64;
+    v = wave_reduce(v, op);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();  // lds may still be read by a previous call
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double r = lds[0];
+    for (int w = 1; w < W; ++w) r = op(r, lds[w]);
+    return r;  // every thread holds the block result
+}
+
+struct AddOp { __device__ double operator()(double a, double b) const { return a + b; } };
+struct MaxOp { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+
+constexpr int kDiagVals = 6;  // mass, energy, sum |u|^2, sum u_g (T - T0), max |u|, nonfinite
+
+template <class St> struct DiagArgs {
+    const typename St::TF* fsrc;
+    const typename St::TG* gsrc;
+    uint32_t N;
+    double gbeta, t_base, t0;
+    double* partial;  // [gridDim.x][kDiagVals]
+};
+
+template <int DIM, class St>
+__global__ __launch_bounds__(kBlock) void diag_kernel(DiagArgs<St> a) {
+    __shared__ double lds[kBlock / 64];
+    double acc[kDiagVals] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < a.N; idx += gridDim.x * kBlock) {
+        const auto m = node_moments<DIM, St>(a.fsrc, a.gsrc, a.N, idx, a.gbeta, a.t_base, a.t0);
+        const double uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+        acc[0] += m.rho;
+        acc[1] += m.T;
+        acc[2] += uu;
+        acc[3] += m.u[DIM - 1] * (m.T - a.t0);
+        acc[4] = fmax(acc[4], sqrt(uu));
+        acc[5] += m.nonfinite;
+    }
+    for (int v = 0; v < kDiagVals; ++v) {
+        const double r = v == 4 ? block_reduce<kBlock>(acc[v], MaxOp{}, lds)
+                                : block_reduce<kBlock>(acc[v], AddOp{}, lds);
+        if (threadIdx.x == 0) a.partial[(size_t)blockIdx.x * kDiagVals + v] = r;
+    }
+}
+
+// one block: reduce nblk partial rows in block order
+__global__ __launch_bounds__(1024) void diag_final_kernel(const double* partial, int nblk, double* out) {
+    __shared__ double lds[1024 / 64];
+    for (int v = 0; v < kDiagVals; ++v) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 1024) {
+            const double x = partial[(size_t)b * kDiagVals + v];
+            acc = v == 4 ? fmax(acc, x) : acc + x;
+        }
+        const double r = v == 4 ? block_reduce<1024>(acc, MaxOp{}, lds) : block_reduce<1024>(acc, AddOp{}, lds);
+        if (threadIdx.x == 0) out[v] = r;
+    }
+}
+
+// per-face wall heat flux sums: block b reduces buffer b (face, slot) in FP64
+struct FaceSumArgs {
+    const double* buf[12];
+    uint32_t count[12];
+    double* out;  // [12]
+};
+
+__global__ __launch_bounds__(1024) void face_sum_kernel(FaceSumArgs a) {
+    __shared__ double lds[1024 / 64];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    if (a.buf[b])
+        for (uint32_t i = threadIdx.x; i < a.count[b]; i += 1024) acc += a.buf[b][i];
+    const double r = block_reduce<1024>(acc, AddOp{}, lds);
+    if (threadIdx.x == 0) a.out[b] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void fill_kernel(double* p, size_t n, double v) {
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+}  // namespace lbm

@@ -1,0 +1,770 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// Validates and maps the run parameters (Section 2.1, Eqs. 2-4: the
+// free-fall scaling gives nu = U H sqrt(Pr/Ra), alpha = U H / sqrt(Pr Ra),
+// g beta = U^2 / (dT H) in lattice units), carves the caller's device
+// workspace, and launches the kernels of kernels.hpp on the caller's stream.
+// The library never allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <type_traits>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagBlocks = 1024;
+constexpr uint32_t kStagingNodes = 1u << 20;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+lbm_status set_err(char* buf, lbm_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+FastDiv make_div(uint32_t d) {
+    FastDiv f{d, 0, 0};
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    f.l = l;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+    return f;
+}
+
+bool div_ok(const FastDiv& f, uint32_t limit) {
+    // spot-check the multiply-high division against the hardware divide
+    const uint32_t probes[] = {0u, 1u, f.d - 1, f.d, f.d + 1, 2 * f.d - 1, 2 * f.d,
+                               limit / 2, limit - 1, limit};
+    for (uint32_t x : probes)
+        if (x <= limit && f.div(x) != x / f.d) return false;
+    for (uint32_t x = 0; x < 4096 && x <= limit; ++x)
+        if (f.div(x) != x / f.d) return false;
+    return true;
+}
+
+struct Derived {
+    double v[LBM_D_COUNT];
+};
+
+int qf_of(int dim) { return dim == 2 ? Flow<2>::Q : Flow<3>::Q; }
+int qg_of(int dim) { return dim == 2 ? Heat<2>::Q : Heat<3>::Q; }
+
+size_t elem_f(int storage) {
+    switch (storage) {
+    case LBM_FP32: return 4;
+    case LBM_FP64: return 8;
+    default: return 2;
+    }
+}
+size_t elem_g(int storage) {
+    switch (storage) {
+    case LBM_FP32: case LBM_MIXED_F16_G32: return 4;
+    case LBM_FP64: return 8;
+    default: return 2;
+    }
+}
+
+lbm_status derive(const lbm_params* p, Derived* out, char* err) {
+    if (!p) return set_err(err, LBM_E_INVALID, "null params");
+    if (p->dim != 2 && p->dim != 3) return set_err(err, LBM_E_INVALID, "dim must be 2 or 3");
+    if (p->storage < LBM_FP32 || p->storage > LBM_MIXED_F16_G32)
+        return set_err(err, LBM_E_INVALID, "unknown storage %d", p->storage);
+    if (p->reserved != 0) return set_err(err, LBM_E_INVALID, "reserved must be 0");
+    for (int a = 0; a < 3; ++a)
+        if (p->n[a] < 1) return set_err(err, LBM_E_INVALID, "n[%d] must be >= 1", a);
+    if (p->dim == 2 && p->n[2] != 1) return set_err(err, LBM_E_INVALID, "n[2] must be 1 in 2D");
+    const double Nd = (double)p->n[0] * p->n[1] * p->n[2];
+    if (Nd > 2147483647.0) return set_err(err, LBM_E_INVALID, "more than 2^31-1 nodes");
+    for (int a = 0; a < p->dim; ++a) {
+        const int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
+        if (lo < 0 || lo > 2 || hi < 0 || hi > 2)
+            return set_err(err, LBM_E_INVALID, "unknown boundary kind on axis %d", a);
+        if ((lo == LBM_BC_PERIODIC) != (hi == LBM_BC_PERIODIC))
+            return set_err(err, LBM_E_INVALID, "periodic faces of axis %d must be paired", a);
+        if (lo != LBM_BC_PERIODIC && p->n[a] < 2)
+            return set_err(err, LBM_E_INVALID, "walled axis %d needs n >= 2", a);
+    }
+    const int gaxis = p->dim - 1;
+    const double H = p->n[gaxis];
+    const double dT = p->t_hot - p->t_cold;
+    const double T0 = 0.5 * (p->t_hot + p->t_cold);
+    const bool derived = std::isnan(p->nu) || std::isnan(p->alpha) || std::isnan(p->gbeta);
+    if (derived) {
+        if (!(p->ra > 0) || !(p->pr > 0)) return set_err(err, LBM_E_INVALID, "ra and pr must be > 0");
+        if (!(p->u_ff > 0) || p->u_ff > 0.3) return set_err(err, LBM_E_INVALID, "u_ff must lie in (0, 0.3]");
+        if (!(dT > 0)) return set_err(err, LBM_E_INVALID, "t_hot must exceed t_cold");
+    }
+    const double nu = std::isnan(p->nu) ? p->u_ff * H * std::sqrt(p->pr / p->ra) : p->nu;
+    const double alpha = std::isnan(p->alpha) ? p->u_ff * H / std::sqrt(p->pr * p->ra) : p->alpha;
+    const double gbeta = std::isnan(p->gbeta) ? p->u_ff * p->u_ff / (dT * H) : p->gbeta;
+    if (!(nu > 0) || !(alpha > 0) || !std::isfinite(gbeta))
+        return set_err(err, LBM_E_INVALID, "nu and alpha must be > 0 and g beta finite");
+    const double a_t = std::isnan(p->a_t) ? (p->dim == 2 ? Heat<2>::a_t_default : Heat<3>::a_t_default) : p->a_t;
+    if (!(a_t < 1.0) || !(a_t > (p->dim == 2 ? -4.0 : -6.0)))
+        return set_err(err, LBM_E_INVALID, "a_t must lie in (%d, 1)", p->dim == 2 ? -4 : -6);
+    const double w_move = p->dim == 2 ? Heat<2>::w_move(a_t) : Heat<3>::w_move(a_t);
+    const double omega = 2.0 * w_move;  // (4 + a_T)/10 or (6 + a_T)/21
+    const double cs2_t = 2.0 * w_move;
+    const double tau_f = 3.0 * nu + 0.5;
+    const double tau_g = alpha / cs2_t + 0.5;
+    const double s_nu = 1.0 / tau_f;
+    const double s_q = std::isnan(p->s_q) ? 8.0 * (2.0 - s_nu) / (8.0 - s_nu) : p->s_q;
+    const double s_e = std::isnan(p->s_e) ? s_nu : p->s_e;
+    const double s_eps = std::isnan(p->s_eps) ? s_nu : p->s_eps;
+    const double s_pi = std::isnan(p->s_pi) ? s_nu : p->s_pi;
+    const double s_m = std::isnan(p->s_m) ? s_q : p->s_m;
+    const double q_j = 1.0 / tau_g;
+    const double q_e = std::isnan(p->q_e) ? 1.0 : p->q_e;
+    const double q_nu = std::isnan(p->q_nu) ? 1.0 : p->q_nu;
+    const double rates[] = {s_nu, s_q, s_e, s_eps, s_pi, s_m, q_j, q_e, q_nu};
+    for (double r : rates)
+        if (!(r > 0.0 && r < 2.0))
+            return set_err(err, LBM_E_INVALID,
+                           "relaxation rates must lie in (0, 2) (tau_f = %g, tau_g = %g)", tau_f, tau_g);
+    double* v = out->v;
+    v[LBM_D_NU] = nu; v[LBM_D_ALPHA] = alpha; v[LBM_D_GBETA] = gbeta;
+    v[LBM_D_TAU_F] = tau_f; v[LBM_D_TAU_G] = tau_g; v[LBM_D_S_NU] = s_nu;
+    v[LBM_D_S_E] = s_e; v[LBM_D_S_EPS] = s_eps; v[LBM_D_S_Q] = s_q;
+    v[LBM_D_S_PI] = s_pi; v[LBM_D_S_M] = s_m; v[LBM_D_Q_J] = q_j;
+    v[LBM_D_Q_E] = q_e; v[LBM_D_Q_NU] = q_nu; v[LBM_D_A_T] = a_t;
+    v[LBM_D_OMEGA] = omega; v[LBM_D_CS2_T] = cs2_t; v[LBM_D_T0] = T0; v[LBM_D_H] = H;
+    return LBM_OK;
+}
+
+struct Layout {
+    size_t pop_bytes, f_bytes;     // one population buffer; its f part
+    size_t off_pop[2], off_flux, off_red, off_stage, total;
+    size_t area[6];                // face node counts (0 for unused faces)
+    size_t flux_doubles;           // per slot
+    size_t red_doubles, stage_nodes;
+};
+
+Layout layout(const lbm_params* p) {
+    Layout L{};
+    const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
+    L.f_bytes = N * qf_of(p->dim) * elem_f(p->storage);
+    L.pop_bytes = L.f_bytes + N * qg_of(p->dim) * elem_g(p->storage);
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2;
+        L.area[f] = a < p->dim ? N / p->n[a] : 0;
+        L.flux_doubles += L.area[f];
+    }
+    L.red_doubles = (size_t)kDiagBlocks * kDiagVals + 64;
+    L.stage_nodes = N < kStagingNodes ? N : kStagingNodes;
+    size_t off = 0;
+    L.off_pop[0] = off; off = align_up(off + L.pop_bytes);
+    L.off_pop[1] = off; off = align_up(off + L.pop_bytes);
+    L.off_flux = off; off = align_up(off + 2 * L.flux_doubles * sizeof(double));
+    L.off_red = off; off = align_up(off + L.red_doubles * sizeof(double));
+    L.off_stage = off; off = align_up(off + L.stage_nodes * (2 + p->dim) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p;
+    Derived d;
+    Layout lay;
+    int device;
+    hipStream_t stream;
+    char* ws;
+    int cur;      // population buffer holding the state
+    int64_t t;    // time step of the state; -1 before init
+    Geometry geo;
+    double t_base;
+    int cond_axis;
+    char err[512];
+
+    void* pop(int k) const { return ws + lay.off_pop[k]; }
+    double* flux(int slot, int face) const {
+        double* base = (double*)(ws + lay.off_flux) + (size_t)slot * lay.flux_doubles;
+        for (int f = 0; f < face; ++f) base += lay.area[f];
+        return base;
+    }
+    double* red() const { return (double*)(ws + lay.off_red); }
+    double* stage() const { return (double*)(ws + lay.off_stage); }
+};
+
+#define HIP_TRY(buf, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return set_err(buf, LBM_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+template <class R> Coef<R> make_coef(const lbm_ctx* c) {
+    Coef<R> k{};
+    const double* v = c->d.v;
+    auto flow_rate = [&](int kind) {
+        switch (kind) {
+        case kE: return v[LBM_D_S_E];
+        case kEps: return v[LBM_D_S_EPS];
+        case kQ: return v[LBM_D_S_Q];
+        case kNu: return v[LBM_D_S_NU];
+        case kPi: return v[LBM_D_S_PI];
+        case kM: return v[LBM_D_S_M];
+        default: return 0.0;
+        }
+    };
+    auto heat_rate = [&](int kind) {
+        switch (kind) {
+        case kJx: case kJy: case kJz: return v[LBM_D_Q_J];
+        case kE: return v[LBM_D_Q_E];
+        case kNu: return v[LBM_D_Q_NU];
+        default: return 0.0;
+        }
+    };
+    const int qf = qf_of(c->p.dim), qg = qg_of(c->p.dim);
+    for (int r = 0; r < qf; ++r) {
+        const int kind = c->p.dim == 2 ? Flow<2>::kind[r] : Flow<3>::kind[r];
+        const double s = flow_rate(kind);
+        k.s[r] = (R)s;
+        k.b[r] = (R)(1.0 - 0.5 * s);
+    }
+    for (int r = 0; r < qg; ++r) {
+        const int kind = c->p.dim == 2 ? Heat<2>::kind[r] : Heat<3>::kind[r];
+        k.q[r] = (R)heat_rate(kind);
+    }
+    k.a_t = (R)v[LBM_D_A_T];
+    k.gbeta = (R)v[LBM_D_GBETA];
+    k.t_base = (R)c->t_base;
+    k.tb_m_t0 = (R)(c->t_base - v[LBM_D_T0]);
+    for (int f = 0; f < 6; ++f) {
+        const double a = c->geo.dirichlet[f] ? v[LBM_D_OMEGA] * (c->p.t_wall[f] - c->t_base) : 0.0;
+        k.abb[f] = (R)a;
+        k.abb_d[f] = (double)(R)a;  // the value the kernel applies, widened
+    }
+    return k;
+}
+
+// Calls fn(std::integral_constant<int, DIM>{}, St{}) for the context's
+// lattice and storage.
+template <class Fn> lbm_status dispatch(const lbm_ctx* c, Fn&& fn) {
+    const int s = c->p.storage;
+    if (c->p.dim == 2) {
+        std::integral_constant<int, 2> d;
+        switch (s) {
+        case LBM_FP32: return fn(d, StF32{});
+        case LBM_FP64: return fn(d, StF64{});
+        case LBM_FP16_SHIFTED: return fn(d, StF16{});
+        case LBM_BF16_SHIFTED: return fn(d, StBF16{});
+        default: return fn(d, StMix{});
+        }
+    }
+    std::integral_constant<int, 3> d;
+    switch (s) {
+    case LBM_FP32: return fn(d, StF32{});
+    case LBM_FP64: return fn(d, StF64{});
+    case LBM_FP16_SHIFTED: return fn(d, StF16{});
+    case LBM_BF16_SHIFTED: return fn(d, StBF16{});
+    default: return fn(d, StMix{});
+    }
+}
+
+unsigned grid_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+lbm_status enter(lbm_ctx* c) {
+    if (!c) return set_err(g_err, LBM_E_INVALID, "null context");
+    HIP_TRY(c->err, hipSetDevice(c->device));
+    return LBM_OK;
+}
+
+lbm_status require_state(lbm_ctx* c) {
+    if (c->t < 0) return set_err(c->err, LBM_E_STATE, "state not initialised: call lbm_init first");
+    return LBM_OK;
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice;
+}
+
+// split population buffer k into typed f and g pointers
+template <class St> struct Pops {
+    typename St::TF* f;
+    typename St::TG* g;
+};
+template <class St> Pops<St> pops(const lbm_ctx* c, int k) {
+    char* base = (char*)c->pop(k);
+    return {(typename St::TF*)base, (typename St::TG*)(base + c->lay.f_bytes)};
+}
+
+lbm_status launch_init(lbm_ctx* c, int mode, uint32_t n0, uint32_t cnt, uint64_t seed, double amp,
+                       const double* rho, const double* u, const double* T) {
+    return dispatch(c, [&](auto dimc, auto st) -> lbm_status {
+        constexpr int DIM = decltype(dimc)::value;
+        using St = decltype(st);
+        InitArgs<St> a{};
+        const auto P = pops<St>(c, c->cur);
+        a.fdst = P.f;
+        a.gdst = P.g;
+        a.geo = c->geo;
+        a.c = make_coef<typename St::R>(c);
+        a.n0 = n0;
+        a.cnt = cnt;
+        a.mode = mode;
+        a.axis = c->cond_axis;
+        a.t_lo = c->cond_axis >= 0 ? c->p.t_wall[2 * c->cond_axis] : 0.0;
+        a.t_hi = c->cond_axis >= 0 ? c->p.t_wall[2 * c->cond_axis + 1] : 0.0;
+        a.t0 = c->d.v[LBM_D_T0];
+        a.amp = amp;
+        a.seed = seed;
+        a.rho = rho;
+        a.u = u;
+        a.T = T;
+        const double at = c->d.v[LBM_D_A_T];
+        a.w_rest = DIM == 2 ? Heat<2>::w_rest(at) : Heat<3>::w_rest(at);
+        a.w_move = DIM == 2 ? Heat<2>::w_move(at) : Heat<3>::w_move(at);
+        hipLaunchKernelGGL((init_kernel<DIM, St>), dim3(grid_for(cnt)), dim3(kBlock), 0, c->stream, a);
+        HIP_TRY(c->err, hipGetLastError());
+        return LBM_OK;
+    });
+}
+
+lbm_status zero_flux(lbm_ctx* c) {
+    const size_t n = 2 * c->lay.flux_doubles;
+    if (n == 0) return LBM_OK;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<size_t>(grid_for(n), 4096)), dim3(kBlock), 0,
+                       c->stream, (double*)(c->ws + c->lay.off_flux), n, 0.0);
+    HIP_TRY(c->err, hipGetLastError());
+    return LBM_OK;
+}
+
+// sums of the two flux slots of every face: out[slot * 6 + face]
+lbm_status face_sums(lbm_ctx* c, double* host12) {
+    FaceSumArgs a{};
+    for (int slot = 0; slot < 2; ++slot)
+        for (int f = 0; f < 6; ++f) {
+            const int b = slot * 6 + f;
+            a.buf[b] = c->geo.dirichlet[f] ? c->flux(slot, f) : nullptr;
+            a.count[b] = (uint32_t)c->lay.area[f];
+        }
+    a.out = c->red();
+    hipLaunchKernelGGL(face_sum_kernel, dim3(12), dim3(1024), 0, c->stream, a);
+    HIP_TRY(c->err, hipGetLastError());
+    HIP_TRY(c->err, hipMemcpyAsync(host12, c->red(), 12 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char* lbm_version(void) { return "paper_2211_03160_amd lbm 1.0 (gfx950)"; }
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_err; }
+
+lbm_status lbm_derive(const lbm_params* p, double* out) {
+    Derived d;
+    const lbm_status st = derive(p, &d, g_err);
+    if (st) return st;
+    if (out) memcpy(out, d.v, sizeof(d.v));
+    g_err[0] = 0;
+    return LBM_OK;
+}
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+    Derived d;
+    if (derive(p, &d, g_err)) return 0;
+    return layout(p).total;
+}
+
+double lbm_bytes_per_update(const lbm_params* p) {
+    Derived d;
+    if (derive(p, &d, g_err)) return 0.0;
+    return 2.0 * (qf_of(p->dim) * (double)elem_f(p->storage) + qg_of(p->dim) * (double)elem_g(p->storage));
+}
+
+lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t bytes, void* hip_stream, lbm_ctx** out) {
+    if (!out) return set_err(g_err, LBM_E_INVALID, "null output pointer");
+    *out = nullptr;
+    Derived d;
+    lbm_status st = derive(p, &d, g_err);
+    if (st) return st;
+    const Layout lay = layout(p);
+    if (!d_workspace) return set_err(g_err, LBM_E_INVALID, "null workspace");
+    if ((uintptr_t)d_workspace % kAlign) return set_err(g_err, LBM_E_INVALID, "workspace not 256-byte aligned");
+    if (bytes < lay.total)
+        return set_err(g_err, LBM_E_INVALID, "workspace of %zu bytes is smaller than the %zu needed", bytes, lay.total);
+    int dev = 0;
+    HIP_TRY(g_err, hipGetDevice(&dev));
+    if (!is_device_ptr(d_workspace)) return set_err(g_err, LBM_E_INVALID, "workspace is not device memory");
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return set_err(g_err, LBM_E_INVALID, "out of host memory");
+    c->p = *p;
+    c->d = d;
+    c->lay = lay;
+    c->device = dev;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)d_workspace;
+    c->cur = 0;
+    c->t = -1;
+    Geometry& g = c->geo;
+    g.nx = p->n[0];
+    g.ny = p->n[1];
+    g.nz = p->n[2];
+    g.N = g.nx * g.ny * g.nz;
+    g.divx = make_div(g.nx);
+    g.divy = make_div(g.ny);
+    if (!div_ok(g.divx, g.N) || !div_ok(g.divy, g.N / g.nx)) {
+        delete c;
+        return set_err(g_err, LBM_E_UNSUPPORTED, "fast division self-check failed");
+    }
+    for (int a = 0; a < 3; ++a) g.periodic[a] = a >= p->dim || p->bc[2 * a] == LBM_BC_PERIODIC;
+    for (int f = 0; f < 6; ++f) g.dirichlet[f] = f / 2 < p->dim && p->bc[f] == LBM_BC_DIRICHLET;
+    const uint32_t blocks = (g.N + kBlock - 1) / kBlock;
+    g.blocks_per_xcd = (blocks + kXcd - 1) / kXcd;
+    const bool g16 = elem_g(p->storage) == 2;
+    c->t_base = g16 ? d.v[LBM_D_T0] : 0.0;
+    c->cond_axis = -1;
+    const int order[3] = {p->dim - 1, 0, 1};
+    for (int k = 0; k < 3 && c->cond_axis < 0; ++k) {
+        const int a = order[k];
+        if (a < p->dim && g.dirichlet[2 * a] && g.dirichlet[2 * a + 1]) c->cond_axis = a;
+    }
+    c->err[0] = 0;
+    g_err[0] = 0;
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm_init(lbm_ctx* c, uint64_t seed, double amp) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (!std::isfinite(amp)) return set_err(c->err, LBM_E_INVALID, "amp must be finite");
+    c->cur = 0;
+    st = launch_init(c, 0, 0, c->geo.N, seed, amp, nullptr, nullptr, nullptr);
+    if (st) return st;
+    st = zero_flux(c);
+    if (st) return st;
+    c->t = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u, const double* T) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (!u || !T) return set_err(c->err, LBM_E_INVALID, "u and T are required");
+    const int dim = c->p.dim;
+    const size_t N = c->geo.N, S = c->lay.stage_nodes;
+    c->cur = 0;
+    double* sr = c->stage();
+    double* su = sr + S;
+    double* sT = su + (size_t)dim * S;
+    for (size_t n0 = 0; n0 < N; n0 += S) {
+        const size_t cnt = std::min(S, N - n0);
+        if (rho) HIP_TRY(c->err, hipMemcpyAsync(sr, rho + n0, cnt * 8, hipMemcpyHostToDevice, c->stream));
+        for (int a = 0; a < dim; ++a)
+            HIP_TRY(c->err, hipMemcpyAsync(su + a * cnt, u + a * N + n0, cnt * 8, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c->err, hipMemcpyAsync(sT, T + n0, cnt * 8, hipMemcpyHostToDevice, c->stream));
+        st = launch_init(c, 1, (uint32_t)n0, (uint32_t)cnt, 0, 0.0, rho ? sr : nullptr, su, sT);
+        if (st) return st;
+        HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+    }
+    st = zero_flux(c);
+    if (st) return st;
+    HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+    c->t = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (n < 0) return set_err(c->err, LBM_E_INVALID, "n must be >= 0");
+    if ((st = require_state(c))) return st;
+    if (n == 0) return LBM_OK;
+    return dispatch(c, [&](auto dimc, auto stc) -> lbm_status {
+        constexpr int DIM = decltype(dimc)::value;
+        using St = decltype(stc);
+        StepArgs<St> a{};
+        a.geo = c->geo;
+        a.c = make_coef<typename St::R>(c);
+        const dim3 grid(c->geo.blocks_per_xcd * kXcd), block(kBlock);
+        for (int64_t s = 0; s < n; ++s) {
+            const auto A = pops<St>(c, c->cur), B = pops<St>(c, 1 - c->cur);
+            a.fsrc = A.f;
+            a.gsrc = A.g;
+            a.fdst = B.f;
+            a.gdst = B.g;
+            const int slot = (int)((c->t + 1) & 1);
+            for (int f = 0; f < 6; ++f) a.flux[f] = c->flux(slot, f);
+            hipLaunchKernelGGL((step_kernel<DIM, St>), grid, block, 0, c->stream, a);
+            c->cur = 1 - c->cur;
+            c->t += 1;
+        }
+        HIP_TRY(c->err, hipGetLastError());
+        return LBM_OK;
+    });
+}
+
+lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if ((st = require_state(c))) return st;
+    const int dim = c->p.dim;
+    const size_t N = c->geo.N;
+    // counter in the tail of the reduction area, after the diagnostics partials
+    unsigned long long* bad = (unsigned long long*)(c->red() + (size_t)kDiagBlocks * kDiagVals + 32);
+    HIP_TRY(c->err, hipMemsetAsync(bad, 0, sizeof(*bad), c->stream));
+    const bool dev_rho = is_device_ptr(rho), dev_u = is_device_ptr(u), dev_T = is_device_ptr(T);
+    const bool all_dev = (!rho || dev_rho) && (!u || dev_u) && (!T || dev_T);
+    st = dispatch(c, [&](auto dimc, auto stc) -> lbm_status {
+        constexpr int DIM = decltype(dimc)::value;
+        using St = decltype(stc);
+        const auto A = pops<St>(c, c->cur);
+        FieldArgs<St> a{};
+        a.fsrc = A.f;
+        a.gsrc = A.g;
+        a.N = (uint32_t)N;
+        a.gbeta = c->d.v[LBM_D_GBETA];
+        a.t_base = c->t_base;
+        a.t0 = c->d.v[LBM_D_T0];
+        a.nonfinite = bad;
+        if (all_dev) {
+            a.n0 = 0;
+            a.cnt = (uint32_t)N;
+            a.rho = rho;
+            a.u = u;
+            a.T = T;
+            hipLaunchKernelGGL((fields_kernel<DIM, St>), dim3(grid_for(N)), dim3(kBlock), 0, c->stream, a);
+            HIP_TRY(c->err, hipGetLastError());
+            return LBM_OK;
+        }
+        const size_t S = c->lay.stage_nodes;
+        double* sr = c->stage();
+        double* su = sr + S;
+        double* sT = su + (size_t)dim * S;
+        for (size_t n0 = 0; n0 < N; n0 += S) {
+            const size_t cnt = std::min(S, N - n0);
+            a.n0 = (uint32_t)n0;
+            a.cnt = (uint32_t)cnt;
+            a.rho = rho ? sr : nullptr;
+            a.u = u ? su : nullptr;
+            a.T = T ? sT : nullptr;
+            hipLaunchKernelGGL((fields_kernel<DIM, St>), dim3(grid_for(cnt)), dim3(kBlock), 0, c->stream, a);
+            HIP_TRY(c->err, hipGetLastError());
+            const hipMemcpyKind k = hipMemcpyDefault;
+            if (rho) HIP_TRY(c->err, hipMemcpyAsync(rho + n0, sr, cnt * 8, k, c->stream));
+            if (u)
+                for (int d = 0; d < DIM; ++d)
+                    HIP_TRY(c->err, hipMemcpyAsync(u + d * N + n0, su + d * cnt, cnt * 8, k, c->stream));
+            if (T) HIP_TRY(c->err, hipMemcpyAsync(T + n0, sT, cnt * 8, k, c->stream));
+            HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+        }
+        return LBM_OK;
+    });
+    if (st) return st;
+    unsigned long long nbad = 0;
+    HIP_TRY(c->err, hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+    if (nbad) return set_err(c->err, LBM_E_UNSTABLE, "%llu non-finite populations at t = %lld", nbad, (long long)c->t);
+    return LBM_OK;
+}
+
+lbm_status lbm_wall_flux(lbm_ctx* c, double* last, double* prev) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if ((st = require_state(c))) return st;
+    double s[12];
+    if ((st = face_sums(c, s))) return st;
+    const int sl = (int)(c->t & 1), sp = 1 - sl;
+    for (int f = 0; f < 6; ++f) {
+        if (last) last[f] = s[sl * 6 + f];
+        if (prev) prev[f] = s[sp * 6 + f];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_nusselt(lbm_ctx* c, double* nu_hot, double* nu_cold) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if ((st = require_state(c))) return st;
+    if (c->t < 2) return set_err(c->err, LBM_E_STATE, "lbm_nusselt needs at least two steps (t = %lld)", (long long)c->t);
+    double num[2] = {0, 0}, area[2] = {0, 0};
+    const double T0 = c->d.v[LBM_D_T0];
+    for (int f = 0; f < 6; ++f) {
+        if (!c->geo.dirichlet[f] || c->p.t_wall[f] == T0) continue;
+        const int k = c->p.t_wall[f] > T0 ? 0 : 1;
+        area[k] += (double)c->lay.area[f];
+    }
+    if (area[0] == 0.0 || area[1] == 0.0)
+        return set_err(c->err, LBM_E_STATE, "lbm_nusselt needs a hot and a cold Dirichlet face");
+    double s[12];
+    if ((st = face_sums(c, s))) return st;
+    for (int f = 0; f < 6; ++f) {
+        if (!c->geo.dirichlet[f] || c->p.t_wall[f] == T0) continue;
+        const int k = c->p.t_wall[f] > T0 ? 0 : 1;
+        const double q = 0.5 * (s[f] + s[6 + f]);  // mean of the two slots
+        num[k] += (k == 0 ? 1.0 : -1.0) * c->p.n[f / 2] * q;
+    }
+    const double scale = 1.0 / (c->d.v[LBM_D_ALPHA] * (c->p.t_hot - c->p.t_cold));
+    const double nh = num[0] * scale / area[0], nc = num[1] * scale / area[1];
+    if (nu_hot) *nu_hot = nh;
+    if (nu_cold) *nu_cold = nc;
+    if (!std::isfinite(nh) || !std::isfinite(nc))
+        return set_err(c->err, LBM_E_UNSTABLE, "non-finite wall heat flux at t = %lld", (long long)c->t);
+    return LBM_OK;
+}
+
+static lbm_status run_diag(lbm_ctx* c, double* host6) {
+    return dispatch(c, [&](auto dimc, auto stc) -> lbm_status {
+        constexpr int DIM = decltype(dimc)::value;
+        using St = decltype(stc);
+        const auto A = pops<St>(c, c->cur);
+        DiagArgs<St> a{};
+        a.fsrc = A.f;
+        a.gsrc = A.g;
+        a.N = c->geo.N;
+        a.gbeta = c->d.v[LBM_D_GBETA];
+        a.t_base = c->t_base;
+        a.t0 = c->d.v[LBM_D_T0];
+        a.partial = c->red();
+        const int nblk = (int)std::min<size_t>(kDiagBlocks, grid_for(c->geo.N));
+        double* out = c->red() + (size_t)kDiagBlocks * kDiagVals;
+        hipLaunchKernelGGL((diag_kernel<DIM, St>), dim3(nblk), dim3(kBlock), 0, c->stream, a);
+        HIP_TRY(c->err, hipGetLastError());
+        hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(1024), 0, c->stream, (const double*)c->red(), nblk, out);
+        HIP_TRY(c->err, hipGetLastError());
+        HIP_TRY(c->err, hipMemcpyAsync(host6, out, kDiagVals * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+        return LBM_OK;
+    });
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* d) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (!d) return set_err(c->err, LBM_E_INVALID, "null output");
+    if ((st = require_state(c))) return st;
+    double v[kDiagVals];
+    if ((st = run_diag(c, v))) return st;
+    const double N = (double)c->geo.N, H = c->d.v[LBM_D_H];
+    const double alpha = c->d.v[LBM_D_ALPHA], nu = c->d.v[LBM_D_NU];
+    const double dT = c->p.t_hot - c->p.t_cold;
+    d->t = c->t;
+    d->mass = v[0];
+    d->energy = v[1];
+    d->umax = v[4];
+    d->nu_vol = 1.0 + H * (v[3] / N) / (alpha * dT);
+    d->re = std::sqrt(v[2] / N) * H / nu;
+    d->nonfinite = (int64_t)v[5];
+    if (d->nonfinite) return set_err(c->err, LBM_E_UNSTABLE, "%lld non-finite populations", (long long)d->nonfinite);
+    return LBM_OK;
+}
+
+// checkpoint: header, populations of the current buffer, both flux slots
+struct StateHeader {
+    uint64_t magic;
+    int64_t t;
+    int32_t dim, storage, n[3], pad;
+    uint64_t pop_bytes, flux_bytes;
+};
+static const uint64_t kStateMagic = 0x31304d424c544d4full;
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+    if (!c) return 0;
+    return sizeof(StateHeader) + c->lay.pop_bytes + 2 * c->lay.flux_doubles * sizeof(double);
+}
+
+lbm_status lbm_export_state(lbm_ctx* c, void* host, size_t bytes) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if ((st = require_state(c))) return st;
+    if (!host || bytes < lbm_state_bytes(c)) return set_err(c->err, LBM_E_INVALID, "buffer too small");
+    StateHeader h{kStateMagic, c->t, c->p.dim, c->p.storage, {c->p.n[0], c->p.n[1], c->p.n[2]}, 0,
+                  c->lay.pop_bytes, 2 * c->lay.flux_doubles * sizeof(double)};
+    char* out = (char*)host;
+    memcpy(out, &h, sizeof(h));
+    HIP_TRY(c->err, hipMemcpyAsync(out + sizeof(h), c->pop(c->cur), h.pop_bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c->err, hipMemcpyAsync(out + sizeof(h) + h.pop_bytes, c->ws + c->lay.off_flux, h.flux_bytes,
+                                   hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_import_state(lbm_ctx* c, const void* host, size_t bytes) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (!host || bytes < sizeof(StateHeader)) return set_err(c->err, LBM_E_INVALID, "buffer too small");
+    StateHeader h;
+    memcpy(&h, host, sizeof(h));
+    if (h.magic != kStateMagic || h.dim != c->p.dim || h.storage != c->p.storage || h.n[0] != c->p.n[0] ||
+        h.n[1] != c->p.n[1] || h.n[2] != c->p.n[2] || h.pop_bytes != c->lay.pop_bytes ||
+        h.flux_bytes != 2 * c->lay.flux_doubles * sizeof(double) || bytes < lbm_state_bytes(c) || h.t < 0)
+        return set_err(c->err, LBM_E_INVALID, "state buffer does not match this context");
+    const char* in = (const char*)host;
+    c->cur = 0;
+    HIP_TRY(c->err, hipMemcpyAsync(c->pop(0), in + sizeof(h), h.pop_bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c->err, hipMemcpyAsync(c->ws + c->lay.off_flux, in + sizeof(h) + h.pop_bytes, h.flux_bytes,
+                                   hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c->err, hipStreamSynchronize(c->stream));
+    c->t = h.t;
+    return LBM_OK;
+}
+
+lbm_status lbm_lattice(int32_t dim, int32_t which, int32_t* q, int32_t* e, int32_t* M, double* w) {
+    if ((dim != 2 && dim != 3) || (which != 0 && which != 1))
+        return set_err(g_err, LBM_E_INVALID, "dim must be 2 or 3 and which 0 or 1");
+    auto emit = [&](auto L, bool flow, double at) {
+        using T = decltype(L);
+        if (q) *q = T::Q;
+        for (int i = 0; i < T::Q; ++i) {
+            if (e) {
+                e[3 * i] = T::ex[i];
+                e[3 * i + 1] = T::ey[i];
+                e[3 * i + 2] = T::ez[i];
+            }
+            if (M)
+                for (int k = 0; k < T::Q; ++k) M[k * T::Q + i] = T::M(k, i);
+        }
+        if (w) {
+            if constexpr (std::is_same_v<T, Flow<2>> || std::is_same_v<T, Flow<3>>) {
+                for (int i = 0; i < T::Q; ++i) w[i] = T::w[i];
+            } else {
+                for (int i = 0; i < T::Q; ++i) w[i] = i == 0 ? T::w_rest(at) : T::w_move(at);
+            }
+        }
+        (void)flow;
+    };
+    if (dim == 2 && which == 0) emit(Flow<2>{}, true, 0.0);
+    else if (dim == 2) emit(Heat<2>{}, false, Heat<2>::a_t_default);
+    else if (which == 0) emit(Flow<3>{}, true, 0.0);
+    else emit(Heat<3>{}, false, Heat<3>::a_t_default);
+    return LBM_OK;
+}
+
+}  // extern "C"

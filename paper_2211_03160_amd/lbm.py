@@ -1,0 +1,285 @@
+"""ctypes binding of the gfx950 thermal LBM library (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``liblbm.so``.  PyTorch provides the device workspace (a uint8 tensor the
+library carves up) and the stream the kernels are launched on.  There is no
+fallback: if the library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from .build import LIB as LIB_PATH
+
+STORAGE = {"fp32": 0, "fp64": 1, "fp16": 2, "bf16": 3, "mixed": 4}
+BC = {"periodic": 0, "adiabatic": 1, "dirichlet": 2}
+DERIVED = ["nu", "alpha", "gbeta", "tau_f", "tau_g", "s_nu", "s_e", "s_eps",
+           "s_q", "s_pi", "s_m", "q_j", "q_e", "q_nu", "a_t", "omega",
+           "cs2_t", "t0", "H"]
+STATUS = {0: "LBM_OK", -1: "LBM_E_INVALID", -2: "LBM_E_DEVICE",
+          -3: "LBM_E_UNSTABLE", -4: "LBM_E_STATE", -5: "LBM_E_UNSUPPORTED"}
+
+# every entry point declared in include/lbm.h
+EXPORTS = ["lbm_derive", "lbm_workspace_bytes", "lbm_bytes_per_update",
+           "lbm_create", "lbm_init", "lbm_init_fields", "lbm_step",
+           "lbm_fields", "lbm_nusselt", "lbm_wall_flux", "lbm_diagnostics",
+           "lbm_state_bytes", "lbm_export_state", "lbm_import_state",
+           "lbm_time", "lbm_destroy", "lbm_last_error", "lbm_lattice",
+           "lbm_version"]
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3),
+                ("storage", C.c_int32), ("bc", C.c_int32 * 6),
+                ("reserved", C.c_int32), ("t_wall", C.c_double * 6),
+                ("ra", C.c_double), ("pr", C.c_double), ("u_ff", C.c_double),
+                ("t_hot", C.c_double), ("t_cold", C.c_double),
+                ("nu", C.c_double), ("alpha", C.c_double),
+                ("gbeta", C.c_double), ("a_t", C.c_double),
+                ("s_e", C.c_double), ("s_eps", C.c_double),
+                ("s_q", C.c_double), ("s_pi", C.c_double),
+                ("s_m", C.c_double), ("q_e", C.c_double),
+                ("q_nu", C.c_double)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("t", C.c_int64), ("mass", C.c_double),
+                ("energy", C.c_double), ("umax", C.c_double),
+                ("nu_vol", C.c_double), ("re", C.c_double),
+                ("nonfinite", C.c_int64)]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library {LIB_PATH} is not built; run "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        P, dp, sz = C.c_void_p, C.POINTER(C.c_double), C.c_size_t
+        pp = C.POINTER(Params)
+        L.lbm_derive.argtypes = [pp, dp]
+        L.lbm_workspace_bytes.argtypes = [pp]
+        L.lbm_workspace_bytes.restype = sz
+        L.lbm_bytes_per_update.argtypes = [pp]
+        L.lbm_bytes_per_update.restype = C.c_double
+        L.lbm_create.argtypes = [pp, P, sz, P, C.POINTER(P)]
+        L.lbm_init.argtypes = [P, C.c_uint64, C.c_double]
+        L.lbm_init_fields.argtypes = [P, dp, dp, dp]
+        L.lbm_step.argtypes = [P, C.c_int64]
+        L.lbm_fields.argtypes = [P, P, P, P]
+        L.lbm_nusselt.argtypes = [P, dp, dp]
+        L.lbm_wall_flux.argtypes = [P, dp, dp]
+        L.lbm_diagnostics.argtypes = [P, C.POINTER(Diag)]
+        L.lbm_state_bytes.argtypes = [P]
+        L.lbm_state_bytes.restype = sz
+        L.lbm_export_state.argtypes = [P, P, sz]
+        L.lbm_import_state.argtypes = [P, P, sz]
+        L.lbm_time.argtypes = [P]
+        L.lbm_time.restype = C.c_int64
+        L.lbm_destroy.argtypes = [P]
+        L.lbm_destroy.restype = None
+        L.lbm_last_error.argtypes = [P]
+        L.lbm_last_error.restype = C.c_char_p
+        ip = C.POINTER(C.c_int32)
+        L.lbm_lattice.argtypes = [C.c_int32, C.c_int32, ip, ip, ip, dp]
+        L.lbm_version.restype = C.c_char_p
+        for name in ("lbm_derive", "lbm_create", "lbm_init", "lbm_init_fields",
+                     "lbm_step", "lbm_fields", "lbm_nusselt", "lbm_wall_flux",
+                     "lbm_diagnostics", "lbm_export_state", "lbm_import_state",
+                     "lbm_lattice"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(cfg: dict) -> Params:
+    """lbm_params from a run configuration dict (see workloads)."""
+    nan = math.nan
+    p = Params()
+    p.dim = int(cfg["dim"])
+    n = list(cfg["n"]) + [1] * (3 - len(cfg["n"]))
+    for a in range(3):
+        p.n[a] = int(n[a])
+    st = cfg.get("storage", "fp32")
+    p.storage = STORAGE[st] if isinstance(st, str) else int(st)
+    for k, b in enumerate(cfg["bc"]):
+        p.bc[k] = BC[b] if isinstance(b, str) else int(b)
+    tw = cfg.get("t_wall", (0.0,) * 6)
+    for k in range(6):
+        p.t_wall[k] = float(tw[k])
+    for name in ("ra", "pr", "u_ff", "t_hot", "t_cold"):
+        setattr(p, name, float(cfg.get(name, nan)))
+    for name in ("nu", "alpha", "gbeta", "a_t", "s_e", "s_eps", "s_q",
+                 "s_pi", "s_m", "q_e", "q_nu"):
+        v = cfg.get(name)
+        setattr(p, name, nan if v is None else float(v))
+    return p
+
+
+def _raise(status, ctx=None):
+    if status != 0:
+        raise LBMError(status, lib().lbm_last_error(ctx).decode())
+
+
+def derive(cfg: dict) -> dict:
+    out = np.empty(len(DERIVED))
+    _raise(lib().lbm_derive(C.byref(make_params(cfg)), _dp(out)))
+    return dict(zip(DERIVED, out.tolist()))
+
+
+def workspace_bytes(cfg: dict) -> int:
+    nbytes = lib().lbm_workspace_bytes(C.byref(make_params(cfg)))
+    if nbytes == 0:
+        raise LBMError(-1, lib().lbm_last_error(None).decode())
+    return int(nbytes)
+
+
+def bytes_per_update(cfg: dict) -> float:
+    return float(lib().lbm_bytes_per_update(C.byref(make_params(cfg))))
+
+
+def lattice(dim: int, thermal: bool):
+    """Kernel tables: (e[q,3], M[q,q], w[q])."""
+    q = C.c_int32()
+    L = lib()
+    _raise(L.lbm_lattice(dim, int(thermal), C.byref(q), None, None, None))
+    q = q.value
+    e = np.empty(3 * q, np.int32)
+    M = np.empty(q * q, np.int32)
+    w = np.empty(q)
+    ip = C.POINTER(C.c_int32)
+    _raise(L.lbm_lattice(dim, int(thermal), None, e.ctypes.data_as(ip),
+                         M.ctypes.data_as(ip), _dp(w)))
+    return e.reshape(q, 3), M.reshape(q, q), w
+
+
+class Cavity:
+    """One thermal cavity advanced by the fused HIP step on cuda:0.
+
+    The device workspace is a torch uint8 tensor owned by this object; the
+    kernels run on ``stream`` (default: torch's current stream).
+    """
+
+    def __init__(self, cfg: dict, stream=None):
+        import torch
+        self.cfg = dict(cfg)
+        self.dim = int(cfg["dim"])
+        n = list(cfg["n"]) + [1] * (3 - len(cfg["n"]))
+        self.n = tuple(int(v) for v in n)
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self._p = make_params(cfg)
+        nbytes = workspace_bytes(cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _raise(lib().lbm_create(C.byref(self._p), C.c_void_p(self.workspace.data_ptr()),
+                                nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.n
+        return (ny, nx) if self.dim == 2 else (nz, ny, nx)
+
+    def _check(self, st):
+        _raise(st, self._h)
+
+    def init(self, seed: int, amp: float):
+        self._check(lib().lbm_init(self._h, C.c_uint64(seed), float(amp)))
+
+    def init_fields(self, rho, u, T):
+        rho = None if rho is None else np.ascontiguousarray(rho, np.float64).ravel()
+        u = np.ascontiguousarray(u, np.float64).reshape(self.dim, self.N)
+        T = np.ascontiguousarray(T, np.float64).ravel()
+        self._check(lib().lbm_init_fields(self._h, _dp(rho), _dp(u), _dp(T)))
+
+    def step(self, n: int = 1):
+        self._check(lib().lbm_step(self._h, int(n)))
+
+    @property
+    def t(self) -> int:
+        return int(lib().lbm_time(self._h))
+
+    def fields(self, check: bool = True):
+        """(rho, u, T) as FP64 numpy arrays shaped like the grid."""
+        rho = np.empty(self.N)
+        u = np.empty(self.dim * self.N)
+        T = np.empty(self.N)
+        st = lib().lbm_fields(self._h, rho.ctypes.data, u.ctypes.data, T.ctypes.data)
+        if check:
+            self._check(st)
+        return (rho.reshape(self.shape), u.reshape((self.dim,) + self.shape),
+                T.reshape(self.shape))
+
+    def fields_device(self, check: bool = True):
+        """(rho, u, T) as FP64 torch tensors on the device."""
+        import torch
+        rho = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        u = torch.empty(self.dim * self.N, dtype=torch.float64, device="cuda")
+        T = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        st = lib().lbm_fields(self._h, rho.data_ptr(), u.data_ptr(), T.data_ptr())
+        if check:
+            self._check(st)
+        return rho, u, T
+
+    def nusselt(self):
+        a, b = C.c_double(), C.c_double()
+        self._check(lib().lbm_nusselt(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def wall_flux(self):
+        last = np.empty(6)
+        prev = np.empty(6)
+        self._check(lib().lbm_wall_flux(self._h, _dp(last), _dp(prev)))
+        return last, prev
+
+    def diagnostics(self, check: bool = True) -> dict:
+        d = Diag()
+        st = lib().lbm_diagnostics(self._h, C.byref(d))
+        if check:
+            self._check(st)
+        return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    def export_state(self) -> bytes:
+        nbytes = int(lib().lbm_state_bytes(self._h))
+        buf = C.create_string_buffer(nbytes)
+        self._check(lib().lbm_export_state(self._h, C.cast(buf, C.c_void_p), nbytes))
+        return buf.raw
+
+    def import_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        self._check(lib().lbm_import_state(self._h, C.cast(buf, C.c_void_p), len(state)))
+
+    def derived(self) -> dict:
+        return derive(self.cfg)
+
+    def bytes_per_update(self) -> float:
+        return bytes_per_update(self.cfg)
