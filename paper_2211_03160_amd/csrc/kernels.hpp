@@ -10,8 +10,12 @@
 //   collide f in moment space with Guo forcing (Eqs. 5, 6a/6b, 8a);
 //   collide g in moment space (Eqs. 7, 9a);
 //   store f+, g+ at x into buffer B.
-// A and B hold POST-collision populations in structure-of-arrays order
-// (one plane of N values per velocity, x fastest; Section 3.1).
+// A and B hold POST-collision populations in a tiled structure-of-arrays
+// order: nodes keep the flat index x + nx (y + ny z) of Section 3.1, and
+// each tile of kTile consecutive nodes (one wavefront) stores its Q
+// velocity planes back to back, [tile][i][lane].  A wavefront then reads
+// and writes a few contiguous runs of Q x 64 values instead of Q separate
+// streams N apart, which the HBM controllers serve at a higher rate.
 //
 // Arithmetic is carried out on deviations h_i = f_i - w_i (flow) and
 // h^g_i = g_i - w^T_i T_b (thermal, T_b = T0 for 16-bit storage, else 0),
@@ -31,6 +35,12 @@ namespace lbm {
 
 constexpr int kBlock = 256;  // threads per block of the node-parallel kernels
 constexpr int kXcd = 8;      // accelerator complex dies of an MI355X
+constexpr int kTile = 64;    // nodes per storage tile (one wavefront)
+
+// element offset of population i of node `node` in a tiled array of Q planes
+template <int Q> __host__ __device__ __forceinline__ uint32_t pop_at(uint32_t node, int i) {
+    return (node / kTile) * (uint32_t)(Q * kTile) + (uint32_t)(i * kTile) + node % kTile;
+}
 
 // ------------------------------------------------------------------ storage
 // Element codecs: stored type T, dec() to the compute type, enc() from it.
@@ -311,14 +321,15 @@ __device__ __forceinline__ void collide_store(typename St::R* hf, typename St::R
     });
 
     // store post-collision populations at the node
+    const uint32_t base_f = pop_at<QF>(idx, 0), base_g = pop_at<QG>(idx, 0);
     static_for<0, QF>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const R v = St::f_dev ? hf[i] : R(L::w[i]) + hf[i];
-        __builtin_nontemporal_store(St::EF::enc(v), fdst + (size_t)i * N + idx);
+        __builtin_nontemporal_store(St::EF::enc(v), fdst + base_f + i * kTile);
     });
     static_for<0, QG>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        __builtin_nontemporal_store(St::EG::enc(hg[i]), gdst + (size_t)i * N + idx);
+        __builtin_nontemporal_store(St::EG::enc(hg[i]), gdst + base_g + i * kTile);
     });
 }
 
@@ -327,7 +338,6 @@ template <int DIM, class St>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
     using R = typename St::R;
     using TF = typename St::TF;
-    using TG = typename St::TG;
     using L = Flow<DIM>;
     using H = Heat<DIM>;
     const Geometry& g = a.geo;
@@ -360,9 +370,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
                          (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
         const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
                             (ez > 0 ? ozm : ez < 0 ? ozp : 0);
-        const TF* plane = a.fsrc + (size_t)i * N;
-        TF v = plane[out ? idx : (uint32_t)((int32_t)idx + off)];
-        if (out) v = a.fsrc[(size_t)L::opp[i] * N + idx];  // half-way bounce-back
+        TF v = a.fsrc[pop_at<L::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)];
+        if (out) v = a.fsrc[pop_at<L::Q>(idx, L::opp[i])];  // half-way bounce-back
         const R r = St::EF::dec(v);
         hf[i] = St::f_dev ? r : r - R(L::w[i]);
     });
@@ -373,13 +382,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
                          (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
         const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
                             (ez > 0 ? ozm : ez < 0 ? ozp : 0);
-        const TG* plane = a.gsrc + (size_t)i * N;
-        R r = St::EG::dec(plane[out ? idx : (uint32_t)((int32_t)idx + off)]);
+        R r = St::EG::dec(a.gsrc[pop_at<H::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)]);
         if (out) {
             // the wall this link crosses: axis of e_i, the side it comes from
             constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
             constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
-            const R back = St::EG::dec(a.gsrc[(size_t)H::opp[i] * N + idx]);
+            const R back = St::EG::dec(a.gsrc[pop_at<H::Q>(idx, H::opp[i])]);
             if (g.dirichlet[face]) {
                 r = a.c.abb[face] - back;  // anti-bounce-back
                 const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
@@ -480,7 +488,7 @@ __device__ __forceinline__ NodeMoments<DIM, St> node_moments(const typename St::
     int bad = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const double v = (double)St::EF::dec(fsrc[(size_t)i * N + idx]);
+        const double v = (double)St::EF::dec(fsrc[pop_at<L::Q>(idx, i)]);
         const double h = St::f_dev ? v : v - L::w[i];
         bad += !isfinite(h);
         drho += h;
@@ -490,7 +498,7 @@ __device__ __forceinline__ NodeMoments<DIM, St> node_moments(const typename St::
     }
 #pragma unroll
     for (int i = 0; i < H::Q; ++i) {
-        const double h = (double)St::EG::dec(gsrc[(size_t)i * N + idx]);
+        const double h = (double)St::EG::dec(gsrc[pop_at<H::Q>(idx, i)]);
         bad += !isfinite(h);
         dT += h;
     }

@@ -91,6 +91,9 @@ lbm_status derive(const lbm_params* p, Derived* out, char* err) {
     if (p->dim == 2 && p->n[2] != 1) return set_err(err, LBM_E_INVALID, "n[2] must be 1 in 2D");
     const double Nd = (double)p->n[0] * p->n[1] * p->n[2];
     if (Nd > 2147483647.0) return set_err(err, LBM_E_INVALID, "more than 2^31-1 nodes");
+    // population offsets are 32-bit element indices
+    if ((Nd + kTile) * (p->dim == 2 ? Flow<2>::Q : Flow<3>::Q) > 4294967295.0)
+        return set_err(err, LBM_E_INVALID, "too many nodes for 32-bit population offsets");
     for (int a = 0; a < p->dim; ++a) {
         const int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
         if (lo < 0 || lo > 2 || hi < 0 || hi > 2)
@@ -158,8 +161,9 @@ struct Layout {
 Layout layout(const lbm_params* p) {
     Layout L{};
     const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
-    L.f_bytes = N * qf_of(p->dim) * elem_f(p->storage);
-    L.pop_bytes = L.f_bytes + N * qg_of(p->dim) * elem_g(p->storage);
+    const size_t Np = (N + kTile - 1) / kTile * kTile;  // whole storage tiles
+    L.f_bytes = align_up(Np * qf_of(p->dim) * elem_f(p->storage));
+    L.pop_bytes = L.f_bytes + Np * qg_of(p->dim) * elem_g(p->storage);
     for (int f = 0; f < 6; ++f) {
         const int a = f / 2;
         L.area[f] = a < p->dim ? N / p->n[a] : 0;
