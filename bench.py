@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--quick", action="store_true", help="headline only, no variants")
-    ap.add_argument("--only", default=None, help="run a single case by name and exit")
+    ap.add_argument("--only", default=None, help="comma-separated case names: run those and exit")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (for counter calibration)")
@@ -176,9 +176,10 @@ def main():
         log("copy probe: 3 x 1 GiB device copies done")
 
     if args.only:
-        cfg, w, k = cases[args.only]
-        r = run_case(cfg, w, k, seed, noise, want_nu=False)
-        log(args.only, json.dumps(r))
+        for name in args.only.split(","):
+            cfg, w, k = cases[name]
+            r = run_case(cfg, min(w, args.warmup), min(k, args.steps), seed, noise, want_nu=False)
+            log(name, json.dumps(r))
         return
 
     log(f"headline: 8193^2 D2Q9+D2Q5 FP32, warmup {Wm}, timed {K}")
