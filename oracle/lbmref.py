@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbmref.so")
+# LBMREF_LIB points the binding at another build (the planted-mistake tests
+# load deliberately broken copies of the oracle through it)
+LIB_PATH = os.environ.get("LBMREF_LIB") or os.path.join(HERE, "liblbmref.so")
 
 BC = {"periodic": 0, "adiabatic": 1, "dirichlet": 2}
 DERIVED = ["nu", "alpha", "gbeta", "tau_f", "tau_g", "s_nu", "s_e", "s_eps",
