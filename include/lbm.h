@@ -52,9 +52,10 @@ typedef int32_t lbm_status;
 #define LBM_E_UNSUPPORTED (-5) /* valid request this build cannot serve    */
 
 /* Population storage.  Collision arithmetic is FP32 for every mode except
- * LBM_FP64, which computes in FP64 (the accuracy reference).  The 16-bit
- * modes store f_i - w_i and g_i - w_i^T T0 (w_i^T: rest-state weights of
- * the thermal equilibrium), rounded to nearest even.                    */
+ * LBM_FP64, which computes in FP64 (the accuracy reference).  Every mode
+ * stores the deviations f_i - w_i and g_i - w_i^T T0 (w_i^T: rest-state
+ * weights of the thermal equilibrium); the 16-bit modes round them to
+ * nearest even.                                                         */
 #define LBM_FP32 0
 #define LBM_FP64 1
 #define LBM_FP16_SHIFTED 2

@@ -487,7 +487,9 @@ int lbmref_init(lbmref_ctx* c, uint64_t seed, double amp) {
     double thi = a >= 0 ? c->p.t_wall[2 * a + 1] : c->t0;
     int na = a >= 0 ? c->n[a] : 1;
     double u0[3] = {0, 0, 0};
-    for (size_t idx = 0; idx < c->N; ++idx) {
+#pragma omp parallel for schedule(static) num_threads(lbmref_threads())
+    for (long long ii = 0; ii < (long long)c->N; ++ii) {
+        size_t idx = (size_t)ii;
         int x[3];
         coords(c, idx, x);
         /* conduction profile between the walls, walls half a link out */
@@ -510,7 +512,9 @@ int lbmref_init_fields(lbmref_ctx* c, const double* rho, const double* u,
                        const double* T) {
     if (!c) return LBMREF_E_INVALID;
     if (!u || !T) return fail(c->err, "u and T are required");
-    for (size_t idx = 0; idx < c->N; ++idx) {
+#pragma omp parallel for schedule(static) num_threads(lbmref_threads())
+    for (long long ii = 0; ii < (long long)c->N; ++ii) {
+        size_t idx = (size_t)ii;
         double r = rho ? rho[idx] : 1.0;
         double uu[3] = {0, 0, 0};
         for (int a = 0; a < c->dim; ++a) uu[a] = u[a * c->N + idx];

@@ -447,8 +447,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t bytes, void
     for (int f = 0; f < 6; ++f) g.dirichlet[f] = f / 2 < p->dim && p->bc[f] == LBM_BC_DIRICHLET;
     const uint32_t blocks = (g.N + kBlock - 1) / kBlock;
     g.blocks_per_xcd = (blocks + kXcd - 1) / kXcd;
-    const bool g16 = elem_g(p->storage) == 2;
-    c->t_base = g16 ? d.v[LBM_D_T0] : 0.0;
+    c->t_base = d.v[LBM_D_T0];  // thermal populations are stored as g - w^T T0
     c->cond_axis = -1;
     const int order[3] = {p->dim - 1, 0, 1};
     for (int k = 0; k < 3 && c->cond_axis < 0; ++k) {
