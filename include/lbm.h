@@ -217,6 +217,78 @@ lbm_status lbm_lattice(int32_t dim, int32_t which, int32_t* q, int32_t* e,
 /* Host only.  Version string of the library build.                      */
 const char* lbm_version(void);
 
+/* ------------------------------------------------------------- batches
+ * Many independent cavities of different sizes and parameters (same dim
+ * and storage) advanced together: every lbm_batch_step launch updates all
+ * nodes of all cavities with the per-node arithmetic of lbm_step, so each
+ * cavity evolves exactly as it would alone (the physics is Section 2.2's,
+ * per cavity; batching is a launch strategy).  All cavities share the time
+ * step counter.  The batch workspace holds every cavity's state plus the
+ * work tables; the library never allocates device memory.               */
+typedef struct lbm_batch lbm_batch;
+
+typedef struct lbm_batch_config {
+    int32_t block;       /* threads per block: 128, 256 or 512                */
+    int32_t grid_per_cu; /* 0: one block per work unit of `block` nodes;
+                            k > 0: persistent grid of k blocks per compute
+                            unit, looping over the units                      */
+    int32_t graph_steps; /* 0: launch every step; G > 0 (even): capture G
+                            steps once into a hipGraph and replay it (needs a
+                            non-default stream; ignored on the NULL stream)  */
+    int32_t reserved;    /* 0                                                 */
+} lbm_batch_config;
+
+/* Host only.  Device workspace bytes for `count` cavities with parameters
+ * ps[0..count-1]; 0 if any is invalid or they differ in dim or storage. */
+size_t lbm_batch_workspace_bytes(const lbm_params* ps, int32_t count);
+
+/* count in [1, 65535].  Default config {256, 0, 0}.  d_workspace: device
+ * pointer, 256-byte aligned, caller-owned, at least
+ * lbm_batch_workspace_bytes bytes.                                      */
+lbm_status lbm_batch_create(const lbm_params* ps, int32_t count, void* d_workspace, size_t bytes,
+                            void* hip_stream, lbm_batch** out);
+
+/* lbm_init of every cavity k with seeds[k], amps[k]; clears the
+ * instability flags; t = 0.  Synchronises.                              */
+lbm_status lbm_batch_init(lbm_batch* b, const uint64_t* seeds, const double* amps);
+
+/* lbm_init_fields of cavity k; only at t = 0, after lbm_batch_init.     */
+lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t k, const double* rho, const double* u,
+                                 const double* T);
+
+/* Enqueues n steps of every cavity (graph replays when configured, then
+ * single launches for the remainder).  Asynchronous.                    */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Borrowed view of cavity k, owned by the batch: lbm_fields, lbm_nusselt,
+ * lbm_wall_flux, lbm_diagnostics and lbm_export_state work on it;
+ * lbm_init, lbm_init_fields, lbm_step and lbm_import_state return
+ * LBM_E_STATE; lbm_destroy ignores it.                                  */
+lbm_status lbm_batch_cavity(lbm_batch* b, int32_t k, lbm_ctx** view);
+
+/* Wall Nusselt numbers of every cavity (arrays of count; NaN where a
+ * cavity has no hot or cold face or has diverged).  LBM_E_STATE if t < 2.
+ * Synchronises.                                                         */
+lbm_status lbm_batch_nusselt(lbm_batch* b, double* nu_hot, double* nu_cold);
+
+/* flags[k] = 1 once cavity k produced a non-finite density or temperature
+ * (its divergence does not affect the other cavities).  Synchronises.   */
+lbm_status lbm_batch_unstable(lbm_batch* b, int32_t* flags);
+
+/* Autotuner: times `steps` launches of each candidate launch shape (block
+ * 128/256/512 x grid_per_cu 0/2/4/8) with HIP events on the batch stream
+ * and keeps the fastest (graph_steps is left as configured).  The timing
+ * steps are real steps: t advances by 12 (steps + 1).  ms_per_step
+ * (nullable) receives up to 12 timings, ncand their number.            */
+lbm_status lbm_batch_tune(lbm_batch* b, int32_t steps, lbm_batch_config* best, double* ms_per_step,
+                          int32_t* ncand);
+
+lbm_status lbm_batch_set_config(lbm_batch* b, const lbm_batch_config* cfg);
+lbm_status lbm_batch_get_config(const lbm_batch* b, lbm_batch_config* cfg);
+int64_t lbm_batch_time(const lbm_batch* b);   /* -1 before init          */
+void lbm_batch_destroy(lbm_batch* b);         /* NULL-safe               */
+const char* lbm_batch_last_error(const lbm_batch* b); /* NULL: this thread */
+
 #ifdef __cplusplus
 }
 #endif

@@ -233,8 +233,9 @@ __device__ __forceinline__ R force_mom(int k, const R* u, const R* F) {
 
 // Moments, both collisions and the store of one node.  hf/hg hold the
 // pre-collision deviations on entry.
+// Returns false if the node's density or temperature is not finite.
 template <int DIM, class St>
-__device__ __forceinline__ void collide_store(typename St::R* hf, typename St::R* hg,
+__device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R* hg,
                                               const Coef<typename St::R>& c,
                                               typename St::TF* __restrict__ fdst,
                                               typename St::TG* __restrict__ gdst, uint32_t N,
@@ -329,18 +330,23 @@ __device__ __forceinline__ void collide_store(typename St::R* hf, typename St::R
         constexpr int i = decltype(ic)::value;
         __builtin_nontemporal_store(St::EG::enc(hg[i]), gdst + base_g + i * kTile);
     });
+    return isfinite(drho + dT);
 }
 
 // ----------------------------------------------------------------- the step
+// One fused update of node idx: pull with the wall rules, moments, both
+// collisions, store.  Returns false if the new rho or T is not finite.
 template <int DIM, class St>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
+__device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename St::R>& c,
+                                          const typename St::TF* __restrict__ fsrc,
+                                          const typename St::TG* __restrict__ gsrc,
+                                          typename St::TF* __restrict__ fdst,
+                                          typename St::TG* __restrict__ gdst, double* const* flux,
+                                          uint32_t idx) {
     using R = typename St::R;
     using TF = typename St::TF;
     using L = Flow<DIM>;
     using H = Heat<DIM>;
-    const Geometry& g = a.geo;
-    const uint32_t idx = logical_block(g.blocks_per_xcd) * kBlock + threadIdx.x;
-    if (idx >= g.N) return;
     uint32_t x, y, z;
     coords(g, idx, x, y, z);
 
@@ -358,7 +364,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
     const int32_t oyp = inyp ? sy : -((int32_t)g.ny - 1) * sy;
     const int32_t ozm = inzm ? -sz : ((int32_t)g.nz - 1) * sz;
     const int32_t ozp = inzp ? sz : -((int32_t)g.nz - 1) * sz;
-    const uint32_t N = g.N;
 
     R hf[L::Q], hg[H::Q];
     static_for<0, L::Q>([&](auto ic) {
@@ -368,8 +373,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
                          (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
         const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
                             (ez > 0 ? ozm : ez < 0 ? ozp : 0);
-        TF v = a.fsrc[pop_at<L::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)];
-        if (out) v = a.fsrc[pop_at<L::Q>(idx, L::opp[i])];  // half-way bounce-back
+        TF v = fsrc[pop_at<L::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)];
+        if (out) v = fsrc[pop_at<L::Q>(idx, L::opp[i])];  // half-way bounce-back
         hf[i] = St::EF::dec(v);
     });
     static_for<0, H::Q>([&](auto ic) {
@@ -379,23 +384,68 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
                          (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
         const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
                             (ez > 0 ? ozm : ez < 0 ? ozp : 0);
-        R r = St::EG::dec(a.gsrc[pop_at<H::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)]);
+        R r = St::EG::dec(gsrc[pop_at<H::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)]);
         if (out) {
             // the wall this link crosses: axis of e_i, the side it comes from
             constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
             constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
-            const R back = St::EG::dec(a.gsrc[pop_at<H::Q>(idx, H::opp[i])]);
+            const R back = St::EG::dec(gsrc[pop_at<H::Q>(idx, H::opp[i])]);
             if (g.dirichlet[face]) {
-                r = a.c.abb[face] - back;  // anti-bounce-back
+                r = c.abb[face] - back;  // anti-bounce-back
                 const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
-                a.flux[face][local] = a.c.abb_d[face] - 2.0 * (double)back;
+                flux[face][local] = c.abb_d[face] - 2.0 * (double)back;
             } else {
                 r = back;  // adiabatic bounce-back
             }
         }
         hg[i] = r;
     });
-    collide_store<DIM, St>(hf, hg, a.c, a.fdst, a.gdst, N, idx);
+    return collide_store<DIM, St>(hf, hg, c, fdst, gdst, g.N, idx);
+}
+
+template <int DIM, class St>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
+    const uint32_t idx = logical_block(a.geo.blocks_per_xcd) * kBlock + threadIdx.x;
+    if (idx >= a.geo.N) return;
+    step_node<DIM, St>(a.geo, a.c, a.fsrc, a.gsrc, a.fdst, a.gdst, a.flux, idx);
+}
+
+// --------------------------------------------------------- batched cavities
+// Many independent cavities of any size advance in one launch.  The work is
+// cut into units of BS nodes of one cavity; unit_cavity maps a unit to its
+// cavity, whose descriptor carries geometry, coefficients and buffers.  With
+// a grid smaller than the unit count the blocks loop over units
+// (persistent launch).
+template <class St> struct BatchCavity {
+    Geometry geo;
+    Coef<typename St::R> c;
+    typename St::TF* f[2];   // population buffers A, B
+    typename St::TG* g[2];
+    double* flux[2][6];      // wall heat flux, per slot and face
+    uint32_t unit0;          // first work unit of this cavity
+};
+
+template <class St> struct BatchArgs {
+    const BatchCavity<St>* cav;
+    const uint16_t* unit_cavity;  // [total_units]
+    uint32_t total_units;
+    int32_t src;                  // buffer holding the current state (0: A, 1: B)
+    int32_t slot;                 // flux slot of this step
+    int32_t* unstable;            // per-cavity flag, set on a non-finite node
+};
+
+template <int DIM, class St, int BS>
+__global__ __launch_bounds__(BS) void batch_step_kernel(BatchArgs<St> a) {
+    for (uint32_t unit = blockIdx.x; unit < a.total_units; unit += gridDim.x) {
+        const uint32_t k = a.unit_cavity[unit];
+        const BatchCavity<St>& cv = a.cav[k];
+        const uint32_t idx = (unit - cv.unit0) * BS + threadIdx.x;
+        if (idx < cv.geo.N) {
+            const bool ok = step_node<DIM, St>(cv.geo, cv.c, cv.f[a.src], cv.g[a.src], cv.f[1 - a.src],
+                                               cv.g[1 - a.src], cv.flux[a.slot], idx);
+            if (!ok) a.unstable[k] = 1;
+        }
+    }
 }
 
 // -------------------------------------------------------------- init kernel
@@ -620,6 +670,24 @@ __global__ __launch_bounds__(1024) void face_sum_kernel(FaceSumArgs a) {
 __global__ __launch_bounds__(kBlock) void fill_kernel(double* p, size_t n, double v) {
     for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
         p[i] = v;
+}
+
+// per-cavity wall heat flux sums: block (k, b) reduces buffer b of cavity k
+struct BatchFaceArgs {
+    const double* const* buf;  // [count][12]
+    const uint32_t* len;       // [count][12]
+    double* out;               // [count][12]
+};
+
+__global__ __launch_bounds__(256) void batch_face_sum_kernel(BatchFaceArgs a) {
+    __shared__ double lds[256 / 64];
+    const size_t b = blockIdx.x;
+    const double* p = a.buf[b];
+    double acc = 0.0;
+    if (p)
+        for (uint32_t i = threadIdx.x; i < a.len[b]; i += 256) acc += p[i];
+    const double r = block_reduce<256>(acc, AddOp{}, lds);
+    if (threadIdx.x == 0) a.out[b] = r;
 }
 
 }  // namespace lbm

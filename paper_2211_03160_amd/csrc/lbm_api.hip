@@ -13,7 +13,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "kernels.hpp"
@@ -158,7 +160,7 @@ struct Layout {
     size_t red_doubles, stage_nodes;
 };
 
-Layout layout(const lbm_params* p) {
+Layout layout(const lbm_params* p, size_t staging_cap = kStagingNodes) {
     Layout L{};
     const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
     const size_t Np = (N + kTile - 1) / kTile * kTile;  // whole storage tiles
@@ -170,7 +172,7 @@ Layout layout(const lbm_params* p) {
         L.flux_doubles += L.area[f];
     }
     L.red_doubles = (size_t)kDiagBlocks * kDiagVals + 64;
-    L.stage_nodes = N < kStagingNodes ? N : kStagingNodes;
+    L.stage_nodes = N < staging_cap ? N : staging_cap;
     size_t off = 0;
     L.off_pop[0] = off; off = align_up(off + L.pop_bytes);
     L.off_pop[1] = off; off = align_up(off + L.pop_bytes);
@@ -195,6 +197,7 @@ struct lbm_ctx {
     Geometry geo;
     double t_base;
     int cond_axis;
+    bool view;    // a cavity owned by a batch: the batch steps and initialises it
     char err[512];
 
     void* pop(int k) const { return ws + lay.off_pop[k]; }
@@ -407,13 +410,17 @@ double lbm_bytes_per_update(const lbm_params* p) {
     return 2.0 * (qf_of(p->dim) * (double)elem_f(p->storage) + qg_of(p->dim) * (double)elem_g(p->storage));
 }
 
-lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t bytes, void* hip_stream, lbm_ctx** out) {
+}  // extern "C"
+
+namespace {
+lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void* hip_stream, size_t staging_cap,
+                      bool view, lbm_ctx** out) {
     if (!out) return set_err(g_err, LBM_E_INVALID, "null output pointer");
     *out = nullptr;
     Derived d;
     lbm_status st = derive(p, &d, g_err);
     if (st) return st;
-    const Layout lay = layout(p);
+    const Layout lay = layout(p, staging_cap);
     if (!d_workspace) return set_err(g_err, LBM_E_INVALID, "null workspace");
     if ((uintptr_t)d_workspace % kAlign) return set_err(g_err, LBM_E_INVALID, "workspace not 256-byte aligned");
     if (bytes < lay.total)
@@ -454,19 +461,49 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t bytes, void
         const int a = order[k];
         if (a < p->dim && g.dirichlet[2 * a] && g.dirichlet[2 * a + 1]) c->cond_axis = a;
     }
+    c->view = view;
     c->err[0] = 0;
     g_err[0] = 0;
     *out = c;
     return LBM_OK;
 }
 
-void lbm_destroy(lbm_ctx* c) { delete c; }
+lbm_status reject_view(lbm_ctx* c, const char* what) {
+    return set_err(c->err, LBM_E_STATE, "%s: this cavity belongs to a batch; use the lbm_batch_* calls", what);
+}
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t bytes, void* hip_stream, lbm_ctx** out) {
+    return create_ctx(p, d_workspace, bytes, hip_stream, kStagingNodes, false, out);
+}
+
+void lbm_destroy(lbm_ctx* c) {
+    if (c && !c->view) delete c;
+}
 
 int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+static lbm_status init_impl(lbm_ctx* c, uint64_t seed, double amp);
+static lbm_status init_fields_impl(lbm_ctx* c, const double* rho, const double* u, const double* T);
 
 lbm_status lbm_init(lbm_ctx* c, uint64_t seed, double amp) {
     lbm_status st = enter(c);
     if (st) return st;
+    if (c->view) return reject_view(c, "lbm_init");
+    return init_impl(c, seed, amp);
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u, const double* T) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (c->view) return reject_view(c, "lbm_init_fields");
+    return init_fields_impl(c, rho, u, T);
+}
+
+static lbm_status init_impl(lbm_ctx* c, uint64_t seed, double amp) {
+    lbm_status st;
     if (!std::isfinite(amp)) return set_err(c->err, LBM_E_INVALID, "amp must be finite");
     c->cur = 0;
     st = launch_init(c, 0, 0, c->geo.N, seed, amp, nullptr, nullptr, nullptr);
@@ -477,9 +514,8 @@ lbm_status lbm_init(lbm_ctx* c, uint64_t seed, double amp) {
     return LBM_OK;
 }
 
-lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u, const double* T) {
-    lbm_status st = enter(c);
-    if (st) return st;
+static lbm_status init_fields_impl(lbm_ctx* c, const double* rho, const double* u, const double* T) {
+    lbm_status st;
     if (!u || !T) return set_err(c->err, LBM_E_INVALID, "u and T are required");
     const int dim = c->p.dim;
     const size_t N = c->geo.N, S = c->lay.stage_nodes;
@@ -507,6 +543,7 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u, const
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     lbm_status st = enter(c);
     if (st) return st;
+    if (c->view) return reject_view(c, "lbm_step");
     if (n < 0) return set_err(c->err, LBM_E_INVALID, "n must be >= 0");
     if ((st = require_state(c))) return st;
     if (n == 0) return LBM_OK;
@@ -722,6 +759,7 @@ lbm_status lbm_export_state(lbm_ctx* c, void* host, size_t bytes) {
 lbm_status lbm_import_state(lbm_ctx* c, const void* host, size_t bytes) {
     lbm_status st = enter(c);
     if (st) return st;
+    if (c->view) return reject_view(c, "lbm_import_state");
     if (!host || bytes < sizeof(StateHeader)) return set_err(c->err, LBM_E_INVALID, "buffer too small");
     StateHeader h;
     memcpy(&h, host, sizeof(h));
@@ -771,3 +809,5 @@ lbm_status lbm_lattice(int32_t dim, int32_t which, int32_t* q, int32_t* e, int32
 }
 
 }  // extern "C"
+
+#include "batch.inc"

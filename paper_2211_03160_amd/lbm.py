@@ -29,7 +29,11 @@ EXPORTS = ["lbm_derive", "lbm_workspace_bytes", "lbm_bytes_per_update",
            "lbm_fields", "lbm_nusselt", "lbm_wall_flux", "lbm_diagnostics",
            "lbm_state_bytes", "lbm_export_state", "lbm_import_state",
            "lbm_time", "lbm_destroy", "lbm_last_error", "lbm_lattice",
-           "lbm_version"]
+           "lbm_version", "lbm_batch_workspace_bytes", "lbm_batch_create",
+           "lbm_batch_init", "lbm_batch_init_fields", "lbm_batch_step",
+           "lbm_batch_cavity", "lbm_batch_nusselt", "lbm_batch_unstable",
+           "lbm_batch_tune", "lbm_batch_set_config", "lbm_batch_get_config",
+           "lbm_batch_time", "lbm_batch_destroy", "lbm_batch_last_error"]
 
 
 class Params(C.Structure):
@@ -51,6 +55,15 @@ class Diag(C.Structure):
                 ("energy", C.c_double), ("umax", C.c_double),
                 ("nu_vol", C.c_double), ("re", C.c_double),
                 ("nonfinite", C.c_int64)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("block", C.c_int32), ("grid_per_cu", C.c_int32),
+                ("graph_steps", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {"block": self.block, "grid_per_cu": self.grid_per_cu,
+                "graph_steps": self.graph_steps}
 
 
 class LBMError(RuntimeError):
@@ -99,6 +112,30 @@ def lib():
         ip = C.POINTER(C.c_int32)
         L.lbm_lattice.argtypes = [C.c_int32, C.c_int32, ip, ip, ip, dp]
         L.lbm_version.restype = C.c_char_p
+        bp = C.POINTER(BatchConfig)
+        L.lbm_batch_workspace_bytes.argtypes = [pp, C.c_int32]
+        L.lbm_batch_workspace_bytes.restype = sz
+        L.lbm_batch_create.argtypes = [pp, C.c_int32, P, sz, P, C.POINTER(P)]
+        L.lbm_batch_init.argtypes = [P, C.POINTER(C.c_uint64), dp]
+        L.lbm_batch_init_fields.argtypes = [P, C.c_int32, dp, dp, dp]
+        L.lbm_batch_step.argtypes = [P, C.c_int64]
+        L.lbm_batch_cavity.argtypes = [P, C.c_int32, C.POINTER(P)]
+        L.lbm_batch_nusselt.argtypes = [P, dp, dp]
+        L.lbm_batch_unstable.argtypes = [P, C.POINTER(C.c_int32)]
+        L.lbm_batch_tune.argtypes = [P, C.c_int32, bp, dp, C.POINTER(C.c_int32)]
+        L.lbm_batch_set_config.argtypes = [P, bp]
+        L.lbm_batch_get_config.argtypes = [P, bp]
+        L.lbm_batch_time.argtypes = [P]
+        L.lbm_batch_time.restype = C.c_int64
+        L.lbm_batch_destroy.argtypes = [P]
+        L.lbm_batch_destroy.restype = None
+        L.lbm_batch_last_error.argtypes = [P]
+        L.lbm_batch_last_error.restype = C.c_char_p
+        for name in ("lbm_batch_create", "lbm_batch_init", "lbm_batch_init_fields",
+                     "lbm_batch_step", "lbm_batch_cavity", "lbm_batch_nusselt",
+                     "lbm_batch_unstable", "lbm_batch_tune", "lbm_batch_set_config",
+                     "lbm_batch_get_config"):
+            getattr(L, name).restype = C.c_int32
         for name in ("lbm_derive", "lbm_create", "lbm_init", "lbm_init_fields",
                      "lbm_step", "lbm_fields", "lbm_nusselt", "lbm_wall_flux",
                      "lbm_diagnostics", "lbm_export_state", "lbm_import_state",
@@ -283,3 +320,111 @@ class Cavity:
 
     def bytes_per_update(self) -> float:
         return bytes_per_update(self.cfg)
+
+
+class _View(Cavity):
+    """A cavity owned by a Batch (no workspace of its own)."""
+
+    def __init__(self, batch, k, handle, cfg):
+        self.cfg = dict(cfg)
+        self.dim = int(cfg["dim"])
+        n = list(cfg["n"]) + [1] * (3 - len(cfg["n"]))
+        self.n = tuple(int(v) for v in n)
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self.stream = batch.stream
+        self._batch = batch  # keeps the workspace alive
+        self._h = handle
+
+    def close(self):
+        self._h = None  # owned by the batch
+
+
+class Batch:
+    """Many cavities advanced by one launch per step (lbm_batch_*).
+
+    Runs on its own torch stream (default priority) so that hipGraph capture
+    is available.
+    """
+
+    def __init__(self, cfgs, stream=None):
+        import torch
+        self.cfgs = [dict(c) for c in cfgs]
+        self.count = len(cfgs)
+        arr = (Params * self.count)(*[make_params(c) for c in cfgs])
+        self._arr = arr
+        nbytes = lib().lbm_batch_workspace_bytes(arr, self.count)
+        if nbytes == 0:
+            raise LBMError(-1, lib().lbm_batch_last_error(None).decode())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = C.c_void_p()
+        st = lib().lbm_batch_create(arr, self.count, C.c_void_p(self.workspace.data_ptr()),
+                                    int(nbytes), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise LBMError(st, lib().lbm_batch_last_error(None).decode())
+        self._h = h
+        self.nodes = [int(np.prod(list(c["n"]) + [1] * (3 - len(c["n"])))) for c in cfgs]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise LBMError(st, lib().lbm_batch_last_error(self._h).decode())
+
+    def init(self, seeds, amps):
+        s = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
+        a = np.ascontiguousarray(amps, np.float64)
+        self._check(lib().lbm_batch_init(self._h, s, _dp(a)))
+
+    def init_fields(self, k, rho, u, T):
+        n = self.nodes[k]
+        dim = int(self.cfgs[k]["dim"])
+        rho = None if rho is None else np.ascontiguousarray(rho, np.float64).ravel()
+        u = np.ascontiguousarray(u, np.float64).reshape(dim, n)
+        T = np.ascontiguousarray(T, np.float64).ravel()
+        self._check(lib().lbm_batch_init_fields(self._h, k, _dp(rho), _dp(u), _dp(T)))
+
+    def step(self, n: int = 1):
+        self._check(lib().lbm_batch_step(self._h, int(n)))
+
+    @property
+    def t(self) -> int:
+        return int(lib().lbm_batch_time(self._h))
+
+    def cavity(self, k: int) -> Cavity:
+        h = C.c_void_p()
+        self._check(lib().lbm_batch_cavity(self._h, int(k), C.byref(h)))
+        return _View(self, k, h, self.cfgs[k])
+
+    def nusselt(self):
+        hot = np.empty(self.count)
+        cold = np.empty(self.count)
+        self._check(lib().lbm_batch_nusselt(self._h, _dp(hot), _dp(cold)))
+        return hot, cold
+
+    def unstable(self):
+        f = (C.c_int32 * self.count)()
+        self._check(lib().lbm_batch_unstable(self._h, f))
+        return np.array(f[:], dtype=bool)
+
+    def config(self) -> dict:
+        c = BatchConfig()
+        self._check(lib().lbm_batch_get_config(self._h, C.byref(c)))
+        return c.as_dict()
+
+    def set_config(self, block=256, grid_per_cu=0, graph_steps=0):
+        c = BatchConfig(int(block), int(grid_per_cu), int(graph_steps), 0)
+        self._check(lib().lbm_batch_set_config(self._h, C.byref(c)))
+
+    def tune(self, steps: int = 5):
+        best = BatchConfig()
+        ms = np.zeros(16)
+        n = C.c_int32()
+        self._check(lib().lbm_batch_tune(self._h, int(steps), C.byref(best), _dp(ms), C.byref(n)))
+        return best.as_dict(), ms[: n.value].tolist()

@@ -79,3 +79,27 @@ def with_storage(cfg: dict, storage: str) -> dict:
     out = dict(cfg)
     out["storage"] = storage
     return out
+
+
+def batched_sweep(count: int = 64, seed: int = SEED, storage: str = "fp32",
+                  heights=(129, 257, 513, 1025), aspects=(1, 2, 4),
+                  ra_range=(1e4, 1e8), pr_range=(0.7, 7.0)):
+    """The batched sweep: `count` independent Rayleigh-Benard cells with
+    heights drawn uniformly from `heights`, aspect ratios from `aspects`
+    (width (H - 1) x aspect + 1 nodes, odd when H is odd), Ra log-uniform
+    and Pr uniform over the given ranges, each with its own seed
+    seed + k.  Returns (cfgs, seeds)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    cfgs, seeds = [], []
+    for k in range(count):
+        H = int(rng.choice(heights))
+        G = int(rng.choice(aspects))
+        ra = float(10.0 ** rng.uniform(math.log10(ra_range[0]), math.log10(ra_range[1])))
+        pr = float(rng.uniform(*pr_range))
+        cfgs.append(rayleigh_benard(2, ((H - 1) * G + 1, H), ra=ra, pr=pr, storage=storage))
+        seeds.append(seed + k)
+    return cfgs, seeds
+
+
+C3 = dict(name="batch64_rb2d", steps=200, warmup=20, noise=NOISE, count=64, seed=SEED)

@@ -1,0 +1,216 @@
+"""GPU tests of the batched launch (lbm_batch_*): every cavity of a batch
+must evolve exactly as the same cavity run alone (the per-node arithmetic is
+shared), under every launch shape, with and without hipGraph replay, and a
+diverging cavity must not disturb the others.  One FP64 batch member is also
+compared with the CPU oracle."""
+import numpy as np
+import pytest
+
+from oracle.lbmref import Oracle
+from paper_2211_03160_amd import lbm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(storage="fp32", dim=2):
+    if dim == 2:
+        return [
+            W.rayleigh_benard(2, (33, 17), ra=2e4, pr=0.71, storage=storage),
+            W.rayleigh_benard(2, (65, 65), ra=1e5, pr=3.0, storage=storage),
+            W.side_heated(2, (41, 41), ra=1e6, storage=storage),
+            W.rayleigh_benard(2, (66, 33), ra=5e4, pr=0.71, lateral="periodic", storage=storage),
+            W.rayleigh_benard(2, (257, 5), ra=1e4, pr=1.5, storage=storage),
+            W.rayleigh_benard(2, (3, 2), ra=1e4, pr=0.9, storage=storage),
+        ]
+    return [
+        W.rayleigh_benard(3, (17, 19, 21), ra=1e5, pr=0.71, storage=storage),
+        W.side_heated(3, (15, 15, 15), ra=1e5, storage=storage),
+        W.rayleigh_benard(3, (12, 10, 9), ra=5e4, pr=0.71, lateral="periodic", storage=storage),
+    ]
+
+
+def _fields_equal(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def _singles(cfgs, seeds, amps, steps):
+    out = []
+    for c, s, a in zip(cfgs, seeds, amps):
+        g = lbm.Cavity(c)
+        g.init(s, a)
+        g.step(steps)
+        out.append((g.fields(), g.nusselt() if _has_nu(c) else None))
+    return out
+
+
+def _has_nu(cfg):
+    return "dirichlet" in cfg["bc"]
+
+
+@pytest.mark.parametrize("dim,storage", [(2, "fp32"), (2, "mixed"), (3, "fp32"), (2, "fp64")])
+def test_batch_members_equal_single_runs(dim, storage):
+    cfgs = _small_batch(storage, dim)
+    seeds = [11 + k for k in range(len(cfgs))]
+    amps = [1e-2] * len(cfgs)
+    steps = 60
+    ref = _singles(cfgs, seeds, amps, steps)
+    b = lbm.Batch(cfgs)
+    b.init(seeds, amps)
+    b.step(steps)
+    assert b.t == steps
+    hot, cold = b.nusselt()
+    for k in range(len(cfgs)):
+        v = b.cavity(k)
+        assert v.t == steps
+        assert _fields_equal(v.fields(), ref[k][0]), k
+        if ref[k][1] is not None:
+            assert (hot[k], cold[k]) == ref[k][1], k
+            assert v.nusselt() == ref[k][1]
+        else:
+            assert np.isnan(hot[k]) and np.isnan(cold[k])
+    assert not b.unstable().any()
+
+
+def test_batch_fp64_member_matches_oracle():
+    cfgs = _small_batch("fp64", 2)
+    seeds = [3] * len(cfgs)
+    b = lbm.Batch(cfgs)
+    b.init(seeds, [1e-2] * len(cfgs))
+    b.step(150)
+    for k in (1, 2):
+        o = Oracle(cfgs[k])
+        o.init(3, 1e-2)
+        o.step(150)
+        rg, ug, Tg = b.cavity(k).fields()
+        ro, uo, To = o.fields()
+        assert max(np.abs(rg - ro).max(), np.abs(ug - uo).max(), np.abs(Tg - To).max()) < 1e-11
+        hot, cold = b.nusselt()
+        nh, nc = o.nusselt()
+        assert abs(hot[k] - nh) < 1e-10 and abs(cold[k] - nc) < 1e-10
+
+
+@pytest.mark.parametrize("block", [128, 256, 512])
+@pytest.mark.parametrize("grid_per_cu", [0, 1, 4])
+def test_launch_shapes_give_identical_results(block, grid_per_cu):
+    cfgs = _small_batch("fp32", 2)
+    seeds = list(range(len(cfgs)))
+    amps = [1e-2] * len(cfgs)
+    base = lbm.Batch(cfgs)
+    base.init(seeds, amps)
+    base.step(25)
+    b = lbm.Batch(cfgs)
+    b.set_config(block=block, grid_per_cu=grid_per_cu)
+    assert b.config() == {"block": block, "grid_per_cu": grid_per_cu, "graph_steps": 0}
+    b.init(seeds, amps)
+    b.step(25)
+    for k in range(len(cfgs)):
+        assert _fields_equal(b.cavity(k).fields(), base.cavity(k).fields())
+
+
+def test_graph_replay_matches_eager():
+    """Replays separated by the program's own work and synchronisations,
+    every replay checked against the eager run."""
+    import torch
+    cfgs = _small_batch("fp32", 2)
+    seeds = list(range(len(cfgs)))
+    amps = [1e-2] * len(cfgs)
+    eager = lbm.Batch(cfgs)
+    graph = lbm.Batch(cfgs)
+    graph.set_config(block=256, grid_per_cu=0, graph_steps=4)
+    eager.init(seeds, amps)
+    graph.init(seeds, amps)
+    for rep in range(5):
+        n = 4 if rep != 2 else 9  # 9 = two replays and one single launch
+        eager.step(n)
+        graph.step(n)
+        x = torch.randn(1024, device="cuda")  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert float((x * 0).sum()) == 0.0
+        assert graph.t == eager.t
+        for k in range(len(cfgs)):
+            assert _fields_equal(graph.cavity(k).fields(), eager.cavity(k).fields()), (rep, k)
+        assert np.array_equal(np.nan_to_num(graph.nusselt()[0]), np.nan_to_num(eager.nusselt()[0]))
+
+
+def test_diverging_cavity_is_flagged_and_isolated():
+    cfgs = _small_batch("fp32", 2)
+    seeds = list(range(len(cfgs)))
+    amps = [1e-2] * len(cfgs)
+    ref = _singles(cfgs, seeds, amps, 30)
+    b = lbm.Batch(cfgs)
+    b.init(seeds, amps)
+    bad = 1
+    n = int(np.prod(cfgs[bad]["n"]))
+    T = np.full(n, 0.5)
+    T[n // 2] = np.nan
+    b.init_fields(bad, None, np.zeros((2, n)), T)
+    b.step(30)
+    flags = b.unstable()
+    assert flags[bad] and flags.sum() == 1
+    for k in range(len(cfgs)):
+        if k != bad:
+            assert _fields_equal(b.cavity(k).fields(), ref[k][0]), k
+    hot, _ = b.nusselt()
+    assert np.isfinite(hot[0])
+
+
+def test_autotuner_picks_a_candidate_and_keeps_results():
+    cfgs = _small_batch("fp32", 2)
+    seeds = list(range(len(cfgs)))
+    amps = [1e-2] * len(cfgs)
+    b = lbm.Batch(cfgs)
+    b.init(seeds, amps)
+    best, ms = b.tune(steps=2)
+    assert len(ms) == 12 and all(m > 0 for m in ms)
+    assert best["block"] in (128, 256, 512) and best["grid_per_cu"] in (0, 2, 4, 8)
+    assert b.config() == best
+    t = b.t
+    assert t == 12 * 3
+    ref = _singles(cfgs, seeds, amps, t + 10)
+    b.step(10)
+    for k in range(len(cfgs)):
+        assert _fields_equal(b.cavity(k).fields(), ref[k][0]), k
+
+
+def test_views_refuse_stepping_and_batch_errors():
+    cfgs = _small_batch("fp32", 2)
+    b = lbm.Batch(cfgs)
+    with pytest.raises(lbm.LBMError):
+        b.step(1)  # before init
+    b.init([1] * len(cfgs), [0.0] * len(cfgs))
+    v = b.cavity(0)
+    for call in (lambda: v.step(1), lambda: v.init(1, 0.0)):
+        with pytest.raises(lbm.LBMError) as e:
+            call()
+        assert e.value.status == -4
+    with pytest.raises(lbm.LBMError):
+        b.set_config(block=100)
+    with pytest.raises(lbm.LBMError):
+        b.set_config(graph_steps=3)
+    b.step(1)
+    with pytest.raises(lbm.LBMError) as e:
+        b.init_fields(0, None, np.zeros((2, 33 * 17)), np.zeros(33 * 17))
+    assert e.value.status == -4
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch([W.rayleigh_benard(2, (9, 9), ra=1e4, pr=0.7, storage="fp32"),
+                   W.rayleigh_benard(2, (9, 9), ra=1e4, pr=0.7, storage="fp64")])
+
+
+def test_sweep_recipe_runs_and_tunes():
+    """The 64-cavity sweep: all members advance; the few under-resolved ones
+    (relaxation times within 1% of 1/2) may be flagged, no other."""
+    cfgs, seeds = W.batched_sweep()
+    b = lbm.Batch(cfgs)
+    b.init(seeds, [W.NOISE] * len(cfgs))
+    best, ms = b.tune(steps=2)
+    b.set_config(graph_steps=10, **{k: best[k] for k in ("block", "grid_per_cu")})
+    b.step(40)
+    flags = b.unstable()
+    taus = [lbm.derive(c) for c in cfgs]
+    for k, f in enumerate(flags):
+        if f:
+            assert min(taus[k]["tau_f"], taus[k]["tau_g"]) < 0.51, k
+    hot, cold = b.nusselt()
+    ok = ~flags
+    assert np.all(np.isfinite(hot[ok])) and np.all(np.isfinite(cold[ok]))
+    print("sweep tune", best, ms, "flagged", int(flags.sum()), flush=True)
