@@ -265,6 +265,19 @@ def main():
         variants["batch64_rb2d_fp32"] = bs
         log("batch64_rb2d_fp32", json.dumps(bs))
 
+        # the paper's own cavity (side-heated, Section 2.3) at its 2D size
+        sh = run_case(W.side_heated(2, (8193, 8193), ra=1e8, storage="fp32"), Wm, K, seed, noise)
+        variants["sh2d_8193_fp32"] = sh
+        log("sh2d_8193_fp32", json.dumps(sh))
+
+        # learned warm start, small steady-regime size: data, training and
+        # evaluation on the GPU (the 257^2 run is `python -m
+        # paper_2211_03160_amd.warmstart`)
+        from paper_2211_03160_amd import warmstart as WS
+        ws = WS.run(**WS.QUICK)
+        variants["warmstart_rb2d_65"] = {k: v for k, v in ws.items() if k not in ("eval", "loss_history")}
+        log("warmstart_rb2d_65", json.dumps(variants["warmstart_rb2d_65"]))
+
     cpu = None if args.no_cpu else cpu_baseline(cfg32)
     if cpu:
         log("cpu baseline", json.dumps(cpu))

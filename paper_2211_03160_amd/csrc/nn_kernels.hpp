@@ -1,0 +1,331 @@
+// nn_kernels.hpp -- BF16 MFMA kernels of the warm-start network (gfx950).
+//
+// Activations and gradients are BF16 tensors in NHWC order with a channel
+// count that is a multiple of 16; products accumulate in FP32 on the matrix
+// cores (v_mfma_f32_16x16x16_bf16).  A 3x3 convolution is an implicit GEMM:
+// M = output pixels, N = output channels, K = 9 taps x input channels.
+// Operand layout of the 16x16x16 instruction (lane l of a wavefront):
+//   A (16 x 16, rows = M): lane l holds A[l % 16][4 (l / 16) + j], j < 4
+//   B (16 x 16, rows = K): lane l holds B[4 (l / 16) + j][l % 16]
+//   D (16 x 16 FP32):      lane l holds D[4 (l / 16) + j][l % 16]
+// Weights are kept as [tap][Cout][Cin] so that the four K values of a B
+// fragment are one 8-byte load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+namespace nn {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // nearest even
+}
+
+struct ConvArgs {
+    const uint16_t* x;   // [P][cin], P = n h w
+    const uint16_t* wt;  // [9][cout][cin]
+    const float* bias;   // [cout] or null
+    uint16_t* y;         // [P][cout]
+    int32_t n, h, w, cin, cout, relu;
+    uint32_t P, ptiles;  // pixels, 16-pixel tiles
+};
+
+// One wavefront computes 16 pixels x (16 NT) output channels.
+template <int NT>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t groups = (uint32_t)a.cout / (16 * NT);
+    if (gw >= a.ptiles * groups) return;
+    const uint32_t pt = gw % a.ptiles, cg = gw / a.ptiles;
+    const uint32_t m = lane & 15, kg = lane >> 4;
+    const uint32_t p = pt * 16 + m;
+    const bool pin = p < a.P;
+    const int32_t pj = pin ? (int32_t)(p % a.w) : 0;
+    const int32_t pi = pin ? (int32_t)((p / a.w) % a.h) : 0;
+    const int32_t pn = pin ? (int32_t)(p / ((uint32_t)a.w * a.h)) : 0;
+    v4f acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int32_t si = pi + tap / 3 - 1, sj = pj + tap % 3 - 1;
+        const bool ok = pin && si >= 0 && si < a.h && sj >= 0 && sj < a.w;
+        const uint16_t* xrow = a.x + ((size_t)((size_t)pn * a.h + (ok ? si : 0)) * a.w + (ok ? sj : 0)) * a.cin;
+        const uint16_t* wtap = a.wt + (size_t)tap * a.cout * a.cin;
+        for (int c0 = 0; c0 < a.cin; c0 += 16) {
+            v4s av = v4s{0, 0, 0, 0};
+            if (ok) av = *(const v4s*)(xrow + c0 + 4 * kg);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const uint32_t co = (cg * NT + t) * 16 + m;
+                const v4s bv = *(const v4s*)(wtap + (size_t)co * a.cin + c0 + 4 * kg);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const uint32_t co = (cg * NT + t) * 16 + m;
+        const float bb = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t q = pt * 16 + 4 * kg + j;
+            if (q < a.P) {
+                float v = acc[t][j] + bb;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                a.y[(size_t)q * a.cout + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// flipped, transposed weights for the data gradient:
+// wf[tap'][ci][co] = wt[8 - tap'][co][ci]
+__global__ void wflip_kernel(const uint16_t* wt, uint16_t* wf, int32_t cin, int32_t cout) {
+    const size_t total = (size_t)9 * cin * cout;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int32_t co = (int32_t)(e % cout);
+        const int32_t ci = (int32_t)((e / cout) % cin);
+        const int32_t tap = (int32_t)(e / ((size_t)cout * cin));
+        wf[e] = wt[((size_t)(8 - tap) * cout + co) * cin + ci];
+    }
+}
+
+struct WGradArgs {
+    const uint16_t* x;   // [P][cin]
+    const uint16_t* dz;  // [P][cout]
+    float* partial;      // [chunks][9][cout][cin]
+    int32_t n, h, w, cin, cout;
+    uint32_t P, chunk;   // pixels per chunk (multiple of 16)
+    uint32_t chunks;
+};
+
+// dW[tap][co][ci] = sum_p dz[p][co] x[p shifted by tap][ci]: M = co,
+// N = ci (4 tiles per wave), K = pixels of one chunk.
+__global__ __launch_bounds__(256) void wgrad_kernel(WGradArgs a) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // input channels in groups of up to four 16-wide tiles per wavefront
+    const uint32_t cot = (uint32_t)a.cout / 16, cit = ((uint32_t)a.cin + 63) / 64;
+    const uint32_t per_chunk = 9 * cot * cit;
+    if (gw >= per_chunk * a.chunks) return;
+    const uint32_t chunk = gw / per_chunk, r = gw % per_chunk;
+    const uint32_t tap = r / (cot * cit), cb = (r / cit) % cot, ib = r % cit;
+    const int rest = a.cin / 16 - (int)ib * 4;
+    const int NTc = rest < 4 ? rest : 4;
+    const int32_t di = (int32_t)tap / 3 - 1, dj = (int32_t)tap % 3 - 1;
+    const uint32_t m = lane & 15, kg = lane >> 4;
+    v4f acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const uint32_t p_begin = chunk * a.chunk;
+    const uint32_t p_end = p_begin + a.chunk < a.P ? p_begin + a.chunk : a.P;
+    for (uint32_t p0 = p_begin; p0 < p_end; p0 += 16) {
+        v4s av;
+        int32_t src[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t p = p0 + 4 * kg + j;
+            uint16_t v = 0;
+            src[j] = -1;
+            if (p < p_end) {
+                v = a.dz[(size_t)p * a.cout + cb * 16 + m];
+                const int32_t pj = (int32_t)(p % a.w), pi = (int32_t)((p / a.w) % a.h);
+                const int32_t pn = (int32_t)(p / ((uint32_t)a.w * a.h));
+                const int32_t si = pi + di, sj = pj + dj;
+                if (si >= 0 && si < a.h && sj >= 0 && sj < a.w) src[j] = (pn * a.h + si) * a.w + sj;
+            }
+            av[j] = (short)v;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t < NTc) {
+                v4s bv;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bv[j] = src[j] >= 0 ? (short)a.x[(size_t)src[j] * a.cin + (ib * 4 + t) * 16 + m] : (short)0;
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    float* out = a.partial + ((size_t)chunk * 9 + tap) * a.cout * a.cin;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t < NTc) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t co = cb * 16 + 4 * kg + j;
+                const uint32_t ci = (ib * 4 + t) * 16 + m;
+                out[(size_t)co * a.cin + ci] = acc[t][j];
+            }
+        }
+    }
+}
+
+// sum the chunk partials in chunk order: dw[e] = sum_c partial[c][e]
+__global__ void sum_chunks_kernel(const float* partial, uint32_t chunks, size_t count, float* dw) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (uint32_t c = 0; c < chunks; ++c) s += partial[(size_t)c * count + e];
+        dw[e] = s;
+    }
+}
+
+// db[co] = sum_p dz[p][co]: one block per channel, fixed reduction order
+__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t* dz, uint32_t P, int32_t cout, float* db) {
+    __shared__ float lds[256];
+    const int32_t co = blockIdx.x;
+    float s = 0.0f;
+    for (uint32_t p = threadIdx.x; p < P; p += 256) s += bf2f(dz[(size_t)p * cout + co]);
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[co] = lds[0];
+}
+
+__global__ void relu_backward_kernel(const uint16_t* y, const uint16_t* dy, uint16_t* dz, size_t count) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+        dz[e] = bf2f(y[e]) > 0.0f ? dy[e] : (uint16_t)0;
+}
+
+// x [n][h][w][c] -> y [n][h/2][w/2][c], 2x2 means
+__global__ void avgpool2_kernel(const uint16_t* x, uint16_t* y, int32_t n, int32_t h, int32_t w, int32_t c) {
+    const size_t total = (size_t)n * (h / 2) * (w / 2) * c;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int32_t ch = (int32_t)(e % c);
+        const size_t q = e / c;
+        const int32_t j = (int32_t)(q % (w / 2)), i = (int32_t)((q / (w / 2)) % (h / 2));
+        const int32_t b = (int32_t)(q / ((size_t)(w / 2) * (h / 2)));
+        const size_t base = (((size_t)b * h + 2 * i) * w + 2 * j) * c + ch;
+        const float s = bf2f(x[base]) + bf2f(x[base + c]) + bf2f(x[base + (size_t)w * c]) +
+                        bf2f(x[base + (size_t)w * c + c]);
+        y[e] = f2bf(0.25f * s);
+    }
+}
+
+// gradient of avgpool2: dx[n][h][w][c] = dy[n][h/2][w/2][c] / 4
+__global__ void avgpool2_backward_kernel(const uint16_t* dy, uint16_t* dx, int32_t n, int32_t h, int32_t w, int32_t c) {
+    const size_t total = (size_t)n * h * w * c;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int32_t ch = (int32_t)(e % c);
+        const size_t q = e / c;
+        const int32_t j = (int32_t)(q % w), i = (int32_t)((q / w) % h), b = (int32_t)(q / ((size_t)w * h));
+        dx[e] = f2bf(0.25f * bf2f(dy[(((size_t)b * (h / 2) + i / 2) * (w / 2) + j / 2) * c + ch]));
+    }
+}
+
+// nearest upsampling x [n][h][w][c] -> y [n][2h][2w][c]
+__global__ void upsample2_kernel(const uint16_t* x, uint16_t* y, int32_t n, int32_t h, int32_t w, int32_t c) {
+    const size_t total = (size_t)n * 4 * h * w * c;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int32_t ch = (int32_t)(e % c);
+        const size_t q = e / c;
+        const int32_t j = (int32_t)(q % (2 * w)), i = (int32_t)((q / (2 * w)) % (2 * h));
+        const int32_t b = (int32_t)(q / ((size_t)4 * w * h));
+        y[e] = x[(((size_t)b * h + i / 2) * w + j / 2) * c + ch];
+    }
+}
+
+// gradient of upsample2: dx[n][h][w][c] = sum of the 2x2 block of dy
+__global__ void upsample2_backward_kernel(const uint16_t* dy, uint16_t* dx, int32_t n, int32_t h, int32_t w, int32_t c) {
+    const size_t total = (size_t)n * h * w * c;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int32_t ch = (int32_t)(e % c);
+        const size_t q = e / c;
+        const int32_t j = (int32_t)(q % w), i = (int32_t)((q / w) % h), b = (int32_t)(q / ((size_t)w * h));
+        const size_t base = (((size_t)b * 2 * h + 2 * i) * 2 * w + 2 * j) * c + ch;
+        const float s = bf2f(dy[base]) + bf2f(dy[base + c]) + bf2f(dy[base + (size_t)2 * w * c]) +
+                        bf2f(dy[base + (size_t)2 * w * c + c]);
+        dx[e] = f2bf(s);
+    }
+}
+
+// dst[p][doff + k] (+)= src[p][soff + k] for k < cc
+__global__ void copy_channels_kernel(const uint16_t* src, int32_t cs, int32_t soff, uint16_t* dst, int32_t cd,
+                                     int32_t doff, int32_t cc, size_t pixels, int32_t accumulate) {
+    const size_t total = pixels * cc;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = e / cc;
+        const int32_t k = (int32_t)(e % cc);
+        const uint16_t v = src[p * cs + soff + k];
+        uint16_t& d = dst[p * cd + doff + k];
+        d = accumulate ? f2bf(bf2f(d) + bf2f(v)) : v;
+    }
+}
+
+// masked MSE over the first `used` channels: per-block partial sums of
+// mask (y - t)^2, and dy = 2 mask (y - t) / count (BF16)
+__global__ __launch_bounds__(256) void mse_kernel(const uint16_t* y, int32_t cy, const float* target,
+                                                  const float* mask, size_t pixels, int32_t used, float inv_count,
+                                                  uint16_t* dy, float* partial) {
+    __shared__ float lds[256];
+    float s = 0.0f;
+    const size_t total = pixels * cy;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = e / cy;
+        const int32_t k = (int32_t)(e % cy);
+        float g = 0.0f;
+        if (k < used) {
+            const float mk = mask[p * used + k];
+            const float d = (bf2f(y[e]) - target[p * used + k]) * mk;
+            s += d * d;
+            g = 2.0f * d * inv_count;
+        }
+        if (dy) dy[e] = f2bf(g);
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = lds[0];
+}
+
+__global__ void sum_partials_kernel(const float* partial, int32_t n, float scale, float* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.0f;
+        for (int32_t i = 0; i < n; ++i) s += partial[i];
+        out[0] = s * scale;
+    }
+}
+
+// Adam (Kingma & Ba, 2015) on FP32 master weights; also refreshes the
+// BF16 copy used by the kernels
+__global__ void adam_kernel(float* w, const float* g, float* m, float* v, size_t count, float lr, float b1, float b2,
+                            float eps, float c1, float c2, uint16_t* wbf) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[e];
+        const float mi = b1 * m[e] + (1.0f - b1) * gi;
+        const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
+        m[e] = mi;
+        v[e] = vi;
+        const float wi = w[e] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[e] = wi;
+        if (wbf) wbf[e] = f2bf(wi);
+    }
+}
+
+__global__ void f32_to_bf16_kernel(const float* src, uint16_t* dst, size_t count) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+        dst[e] = f2bf(src[e]);
+}
+
+__global__ void bf16_to_f32_kernel(const uint16_t* src, float* dst, size_t count) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+        dst[e] = bf2f(src[e]);
+}
+
+}  // namespace nn
+}  // namespace lbm

@@ -1,0 +1,314 @@
+"""Learned warm start for Rayleigh-Benard cavities.
+
+A U-Net (paper_2211_03160_amd.nn, BF16 MFMA kernels) maps the conduction
+state of a cavity and its parameters (log Ra, Pr, aspect ratio) to a
+developed convective state (T, u_x, u_y).  The lattice Boltzmann run then
+starts from that state (lbm_batch_init_fields) instead of from conduction
+plus noise.  Training data are snapshots of the developed flow produced by
+the solver itself (batched runs); the plain run from the conduction state
+is both the fallback and the judge: the evaluation counts the steps each
+start needs until the windowed mean of the wall Nusselt number stays within
+1% of that run's long-time mean, and the error of the warm run's long-time
+Nu against the plain run's.
+
+Grids: the network sees every second node of the cavity (H = 2 Hc - 1 nodes
+become Hc), zero-padded to a multiple of 2^(levels-1); predictions are
+interpolated back to the full grid.  Large-scale rolls come in two mirror
+images; snapshots are mirrored to a clockwise mean circulation so the
+network learns one of them.
+
+Usage: python -m paper_2211_03160_amd.warmstart [--quick] [--out PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import lbm, nn
+from . import workloads as W
+
+U_FF = 0.1
+CIN, COUT = 16, 16
+LOGRA_MID, LOGRA_HALF = 6.5, 1.5
+PR_MID, PR_HALF = 3.85, 3.15
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cavity_cfgs(count, H, ra_range, pr_range, seed, aspect=1, storage="fp32"):
+    rng = np.random.default_rng(seed)
+    cfgs = []
+    for _ in range(count):
+        ra = float(10.0 ** rng.uniform(math.log10(ra_range[0]), math.log10(ra_range[1])))
+        pr = float(rng.uniform(*pr_range))
+        cfgs.append(W.rayleigh_benard(2, ((H - 1) * aspect + 1, H), ra=ra, pr=pr, u_ff=U_FF,
+                                      storage=storage))
+    return cfgs
+
+
+def coarse_shape(cfg, levels):
+    nx, ny = cfg["n"][0], cfg["n"][1]
+    cx, cy = (nx + 1) // 2, (ny + 1) // 2
+    q = 2 ** (levels - 1)
+    return cy, cx, -(-cy // q) * q, -(-cx // q) * q
+
+
+def conduction(cfg):
+    ny = cfg["n"][1]
+    y = (np.arange(ny) + 0.5) / ny
+    return np.repeat((1.0 - y)[:, None], cfg["n"][0], axis=1)
+
+
+def features(cfg, levels):
+    """Network input [Hp, Wp, CIN]: conduction T - 1/2, normalised log Ra,
+    Pr and aspect ratio, and the inside mask, on the coarse grid."""
+    cy, cx, hp, wp = coarse_shape(cfg, levels)
+    x = np.zeros((hp, wp, CIN), np.float32)
+    x[:cy, :cx, 0] = conduction(cfg)[::2, ::2] - 0.5
+    x[:cy, :cx, 1] = (math.log10(cfg["ra"]) - LOGRA_MID) / LOGRA_HALF
+    x[:cy, :cx, 2] = (cfg["pr"] - PR_MID) / PR_HALF
+    x[:cy, :cx, 3] = (cfg["n"][0] - 1) / (cfg["n"][1] - 1) - 1.0
+    x[:cy, :cx, 4] = 1.0
+    return x
+
+
+def canonical(u, T):
+    """Mirror in x if the mean circulation is counter-clockwise."""
+    ux, uy = u[0], u[1]
+    circ = float((np.gradient(uy, axis=1) - np.gradient(ux, axis=0)).mean())
+    if circ > 0:
+        return np.stack([-ux[:, ::-1], uy[:, ::-1]]), T[:, ::-1]
+    return u, T
+
+
+def target(cfg, u, T, levels):
+    """Training target [Hp, Wp, 3] (T - T_cond, u_x / U, u_y / U) and mask."""
+    cy, cx, hp, wp = coarse_shape(cfg, levels)
+    u, T = canonical(u, T)
+    y = np.zeros((hp, wp, 3), np.float32)
+    m = np.zeros((hp, wp, 3), np.float32)
+    y[:cy, :cx, 0] = (T - conduction(cfg))[::2, ::2]
+    y[:cy, :cx, 1] = u[0][::2, ::2] / U_FF
+    y[:cy, :cx, 2] = u[1][::2, ::2] / U_FF
+    m[:cy, :cx, :] = 1.0
+    return y, m
+
+
+def to_full(cfg, pred):
+    """Coarse prediction [Hp, Wp, 3] -> full-grid (u [2][ny][nx], T)."""
+    nx, ny = cfg["n"][0], cfg["n"][1]
+    cy, cx = (ny + 1) // 2, (nx + 1) // 2
+    p = pred[:cy, :cx, :].astype(np.float64)
+    full = np.zeros((ny, nx, 3))
+    full[::2, ::2] = p
+    full[1::2, ::2] = 0.5 * (p[:-1] + p[1:])
+    full[:, 1::2] = 0.5 * (full[:, :-1:2] + full[:, 2::2])
+    T = conduction(cfg) + full[..., 0]
+    u = np.stack([full[..., 1], full[..., 2]]) * U_FF
+    return u, T
+
+
+def generate(cfgs, seeds, steps, snap_from, snap_every, levels, graph_steps=100):
+    """Run the cavities together and collect developed snapshots."""
+    b = lbm.Batch(cfgs)
+    b.init(seeds, [W.NOISE] * len(cfgs))
+    best, _ = b.tune(steps=2)
+    b.set_config(best["block"], best["grid_per_cu"], graph_steps)
+    X = np.stack([features(c, levels) for c in cfgs])
+    xs, ys, ms = [], [], []
+    t0 = time.time()
+    while b.t < steps:
+        nxt = min(steps, snap_from if b.t < snap_from else b.t + snap_every)
+        b.step(nxt - b.t)
+        if b.t >= snap_from:
+            flags = b.unstable()
+            for k, c in enumerate(cfgs):
+                if flags[k]:
+                    continue
+                _, u, T = b.cavity(k).fields()
+                y, m = target(c, u, T, levels)
+                xs.append(X[k])
+                ys.append(y)
+                ms.append(m)
+            log(f"  t = {b.t}: {len(ys)} snapshots ({time.time() - t0:.1f} s)")
+    return np.stack(xs), np.stack(ys), np.stack(ms), int(b.unstable().sum())
+
+
+def train(X, Y, M, chans, epochs, batch, lr, seed, log_every=1):
+    import torch
+    net = nn.UNet(cin=CIN, cout=COUT, chans=chans, seed=seed)
+    Xd = nn.to_bf16(torch.from_numpy(X).cuda())
+    Yd = torch.from_numpy(Y).cuda()
+    Md = torch.from_numpy(M).cuda()
+    rng = np.random.default_rng(seed)
+    hist = []
+    S = X.shape[0]
+    for ep in range(epochs):
+        order = torch.from_numpy(rng.permutation(S)).cuda()
+        tot = 0.0
+        nb = 0
+        rate = lr if ep < int(0.7 * epochs) else lr * 0.3
+        for i in range(0, S - batch + 1, batch):
+            idx = order[i:i + batch]
+            y, tape = net.forward(Xd[idx].contiguous())
+            loss, dy = nn.mse(y, Yd[idx].contiguous(), Md[idx].contiguous())
+            net.backward(tape, dy)
+            net.adam(lr=rate)
+            tot += float(loss.item())
+            nb += 1
+        hist.append(tot / max(nb, 1))
+        if log_every and (ep % log_every == 0 or ep == epochs - 1):
+            log(f"  epoch {ep}: loss {hist[-1]:.5f}")
+    return net, hist
+
+
+def predict(net, cfgs, levels):
+    import torch
+    X = np.stack([features(c, levels) for c in cfgs])
+    y, _ = net.forward(nn.to_bf16(torch.from_numpy(X).cuda()))
+    out = nn.to_f32(y).cpu().numpy()[..., :3]
+    return [to_full(c, out[k]) for k, c in enumerate(cfgs)]
+
+
+def steps_to_steady(hist, every, ref, window, tol=0.01):
+    """First step after which the windowed mean of Nu stays within tol of
+    ref; None if it never settles."""
+    h = np.asarray(hist)
+    if len(h) < window:
+        return None
+    wm = np.convolve(h, np.ones(window) / window, mode="valid")
+    ok = np.abs(wm - ref) <= tol * abs(ref)
+    bad = np.nonzero(~ok)[0]
+    first = 0 if len(bad) == 0 else bad[-1] + 1
+    if first >= len(wm):
+        return None
+    return int((first + window) * every)
+
+
+def evaluate(net, cfgs, seeds, steps, every, levels, window):
+    """Plain (conduction + noise) and warm (network) starts of the same
+    cavities in one batch; Nu = (Nu_hot + Nu_cold)/2 every `every` steps."""
+    n = len(cfgs)
+    b = lbm.Batch(cfgs + cfgs)
+    b.init(list(seeds) + list(seeds), [W.NOISE] * (2 * n))
+    for k, (u, T) in enumerate(predict(net, cfgs, levels)):
+        b.init_fields(n + k, None, u, T)
+    b.set_config(256, 0, every if every % 2 == 0 else 0)
+    hist = []
+    t0 = time.time()
+    while b.t < steps:
+        b.step(every)
+        hot, cold = b.nusselt()
+        hist.append(0.5 * (hot + cold))
+        if len(hist) % max(1, (steps // every) // 10) == 0:
+            log(f"  eval t = {b.t} ({time.time() - t0:.1f} s)")
+    hist = np.array(hist)  # [records][2n]
+    tail = max(window, (3 * len(hist)) // 10)
+    res = []
+    for k in range(n):
+        # each run settles on its own long-time mean (convection cells can
+        # settle in different roll states); the final error compares the
+        # warm run's mean with the plain run's
+        ref = float(hist[-tail:, k].mean())
+        warm_final = float(hist[-tail:, n + k].mean())
+        sp = steps_to_steady(hist[:, k], every, ref, window)
+        sw = steps_to_steady(hist[:, n + k], every, warm_final, window)
+        # statistical uncertainty of the plain run's mean: spread of four
+        # block means over the averaging tail
+        blocks = np.array_split(hist[-tail:, k], 4)
+        sem = float(np.std([b.mean() for b in blocks]) / 2.0) / abs(ref)
+        # unsteady cells fluctuate by more than 1% over any window we can
+        # afford: also count steps into a band of 3 standard errors
+        band = max(0.01, 3.0 * sem)
+        bp = steps_to_steady(hist[:, k], every, ref, window, tol=band)
+        bw = steps_to_steady(hist[:, n + k], every, warm_final, window, tol=band)
+        res.append({"ra": cfgs[k]["ra"], "pr": cfgs[k]["pr"], "nu_plain": ref, "nu_warm": warm_final,
+                    "nu_rel_err_warm": abs(warm_final - ref) / abs(ref), "nu_plain_rel_sem": sem,
+                    "steps_plain": sp, "steps_warm": sw, "band": band,
+                    "steps_plain_band": bp, "steps_warm_band": bw})
+    flags = b.unstable()
+    return res, int(flags.sum())
+
+
+def run(H=257, n_train=128, n_eval=16, steps=200000, snap_from=72000, snap_every=8000,
+        chans=(32, 64, 128, 256), epochs=24, batch=16, lr=1e-3, ra_range=(1e5, 1e8),
+        pr_range=(0.7, 7.0), eval_steps=600000, eval_every=500, window=100, seed=2024):
+    """Defaults: the 257^2 configuration (window = 50000 steps, about 20
+    free-fall times H/U)."""
+    levels = len(chans)
+    out = {"H": H, "chans": list(chans), "ra_range": list(ra_range), "pr_range": list(pr_range)}
+    t0 = time.time()
+    train_cfgs = cavity_cfgs(n_train, H, ra_range, pr_range, seed)
+    X, Y, M = [], [], []
+    flagged = 0
+    for i in range(0, n_train, 64):
+        log(f"data: cavities {i}..{min(n_train, i + 64) - 1}")
+        x, y, m, f = generate(train_cfgs[i:i + 64], [seed + k for k in range(i, min(n_train, i + 64))],
+                              steps, snap_from, snap_every, levels)
+        X.append(x)
+        Y.append(y)
+        M.append(m)
+        flagged += f
+    X, Y, M = np.concatenate(X), np.concatenate(Y), np.concatenate(M)
+    out["snapshots"] = int(X.shape[0])
+    out["unstable_training_cavities"] = flagged
+    out["datagen_s"] = time.time() - t0
+    t1 = time.time()
+    net, hist = train(X, Y, M, chans, epochs, batch, lr, seed)
+    out["train_s"] = time.time() - t1
+    out["loss_history"] = [round(v, 6) for v in hist]
+    t2 = time.time()
+    eval_cfgs = cavity_cfgs(n_eval, H, ra_range, pr_range, seed + 99991)
+    res, bad = evaluate(net, eval_cfgs, [seed + 5000 + k for k in range(n_eval)], eval_steps,
+                        eval_every, levels, window)
+    out["eval_s"] = time.time() - t2
+    out["unstable_eval_runs"] = bad
+    out["eval"] = res
+    sp = [r["steps_plain"] for r in res if r["steps_plain"] is not None and r["steps_warm"] is not None]
+    sw = [r["steps_warm"] for r in res if r["steps_plain"] is not None and r["steps_warm"] is not None]
+    out["median_steps_plain"] = float(np.median(sp)) if sp else None
+    out["median_steps_warm"] = float(np.median(sw)) if sw else None
+    out["mean_steps_saved_fraction"] = float(np.mean([1 - w / p for p, w in zip(sp, sw) if p])) if sp else None
+    out["median_nu_rel_err_warm"] = float(np.median([r["nu_rel_err_warm"] for r in res]))
+    bb = [(r["steps_plain_band"], r["steps_warm_band"]) for r in res
+          if r["steps_plain_band"] is not None and r["steps_warm_band"] is not None]
+    out["median_steps_plain_band"] = float(np.median([p for p, _ in bb])) if bb else None
+    out["median_steps_warm_band"] = float(np.median([w for _, w in bb])) if bb else None
+    out["median_nu_plain_rel_sem"] = float(np.median([r["nu_plain_rel_sem"] for r in res]))
+    out["settled_plain"] = sum(r["steps_plain"] is not None for r in res)
+    out["settled_warm"] = sum(r["steps_warm"] is not None for r in res)
+    out["window_steps"] = window * eval_every
+    return out
+
+
+QUICK = dict(H=65, n_train=64, n_eval=8, steps=40000, snap_from=16000, snap_every=2000,
+             chans=(32, 64), epochs=20, batch=16, ra_range=(1e4, 1e5), eval_steps=80000,
+             eval_every=200, window=16)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    if a.quick:
+        out = run(**QUICK)
+    else:
+        out = run()
+    s = json.dumps(out)
+    print(s, flush=True)
+    if a.out:
+        open(a.out, "w").write(s)
+
+
+if __name__ == "__main__":
+    main()
