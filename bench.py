@@ -73,14 +73,17 @@ def timed_steps(cav, steps):
     return e0.elapsed_time(e1) / steps  # ms
 
 
-def run_case(cfg, warmup, steps, seed, noise, want_nu=True):
+def run_case(cfg, warmup, steps, seed, noise, want_nu=True, steps_per_launch=None):
     import torch
     from paper_2211_03160_amd import lbm
     cav = lbm.Cavity(cfg)
+    if steps_per_launch:
+        cav.steps_per_launch = steps_per_launch
     cav.init(seed, noise)
     cav.step(warmup)
     ms = timed_steps(cav, steps)
     out = {"ms_per_step": ms, "glups": cav.N / (ms * 1e-3) / 1e9,
+           "steps_per_launch": cav.steps_per_launch,
            "bytes_per_update": cav.bytes_per_update()}
     out["hbm_gbs_algorithmic"] = out["glups"] * out["bytes_per_update"]
     if want_nu:
@@ -198,6 +201,7 @@ def main():
 
     cases = {
         "rb2d_8193_fp32": (cfg32, Wm, K),
+        "rb2d_8193_fp32_1": (cfg32, Wm, K),
         "rb2d_8193_fp64": (W.with_storage(cfg32, "fp64"), Wm, K),
         "rb2d_8193_fp16": (W.with_storage(cfg32, "fp16"), Wm, K),
         "rb2d_8193_bf16": (W.with_storage(cfg32, "bf16"), Wm, K),
@@ -220,7 +224,8 @@ def main():
     if args.only:
         for name in args.only.split(","):
             cfg, w, k = cases[name]
-            r = run_case(cfg, min(w, args.warmup), min(k, args.steps), seed, noise, want_nu=False)
+            r = run_case(cfg, min(w, args.warmup), min(k, args.steps), seed, noise, want_nu=False,
+                         steps_per_launch=1 if name.endswith("_1") else None)
             log(name, json.dumps(r))
         return
 
@@ -230,18 +235,29 @@ def main():
     ref64 = run_case(cases["rb2d_8193_fp64"][0], Wm, K, seed, noise)
     log("fp64", json.dumps(ref64))
 
+    # the dominant kernel: two steps per launch (K and W even, so every
+    # timed launch is one), algorithmic bytes = one read and one write of
+    # all populations per node and launch
     N = cfg32["n"][0] * cfg32["n"][1]
+    spl = head["steps_per_launch"]
     bpu = head["bytes_per_update"]
-    launch_s = head["ms_per_step"] * 1e-3
-    achieved = N * bpu / launch_s / 1e9
+    launch_s = head["ms_per_step"] * spl * 1e-3
+    achieved = N * bpu * spl / launch_s / 1e9
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic,
-                "kernel": "lbm::step_kernel<2, StF32>",
+                "kernel": "lbm::step2_kernel<StF32, 19, 4>" if spl == 2 else "lbm::step_kernel<2, StF32>",
+                "steps_per_launch": spl,
+                "launch_ms": round(launch_s * 1e3, 4),
+                "bytes_per_node_per_launch": bpu * spl,
                 "bytes_per_lattice_update": bpu}
 
     variants = {"rb2d_8193_fp64": {**ref64}}
+    one = run_case(cfg32, Wm, K, seed, noise, want_nu=False, steps_per_launch=1)
+    one["hbm_frac"] = one["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
+    variants["rb2d_8193_fp32_one_step_per_launch"] = one
+    log("fp32 one step per launch", json.dumps(one))
     if not args.quick:
         for name in ("rb2d_8193_fp16", "rb2d_8193_bf16", "rb2d_8193_mixed"):
             cfg, w, k = cases[name]

@@ -139,8 +139,9 @@ lbm_status lbm_derive(const lbm_params* p, double* out);
 /* Host only.  Device workspace bytes needed for *p; 0 if *p is invalid. */
 size_t lbm_workspace_bytes(const lbm_params* p);
 
-/* Bytes moved to/from HBM per lattice update by the step kernel in its
- * algorithmic minimum (each population read once and written once).    */
+/* Bytes moved to/from HBM per node and launch by the step kernels in
+ * their algorithmic minimum (each population read once and written once):
+ * per lattice update with one step per launch, per two updates with two. */
 double lbm_bytes_per_update(const lbm_params* p);
 
 /* Creates a context on the current HIP device.  d_workspace: device
@@ -164,8 +165,20 @@ lbm_status lbm_init(lbm_ctx* c, uint64_t seed, double amp);
 lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
                            const double* T);
 
-/* Enqueues n fused steps (n = 0: no-op; n < 0: LBM_E_INVALID).          */
+/* Enqueues n fused steps (n = 0: no-op; n < 0: LBM_E_INVALID).  In 2D
+ * the steps go two per launch by default (see lbm_set_steps_per_launch);
+ * an odd n ends with a single-step launch.                              */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
+
+/* Steps per kernel launch of lbm_step: 1, or 2 (2D only; the default in
+ * 2D).  With 2, each launch computes step t+1 for a tile of nodes and its
+ * one-node ring into on-chip memory and step t+2 of the tile from there:
+ * the update of every node is the same arithmetic on the same stored
+ * values as with 1, so the results are bitwise identical; only the global
+ * memory traffic per step halves.  LBM_E_INVALID for other values,
+ * LBM_E_UNSUPPORTED for 2 in 3D, LBM_E_STATE for a batch member.       */
+lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps);
+int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
 
 /* Moments of the current state at time t (the pre-collision moments
  * rho = sum f, u = (sum e f + F/2)/rho, T = sum g of Section 2.2),

@@ -233,13 +233,30 @@ __device__ __forceinline__ R force_mom(int k, const R* u, const R* F) {
 
 // Moments, both collisions and the store of one node.  hf/hg hold the
 // pre-collision deviations on entry.
+// Destinations of the post-collision populations of one node: the tiled
+// arrays in global memory (non-temporal stores) or a tile in LDS.
+template <class St, int QF, int QG> struct GlobalDst {
+    typename St::TF* f;
+    typename St::TG* g;
+    uint32_t base_f, base_g;
+    __device__ GlobalDst(typename St::TF* f_, typename St::TG* g_, uint32_t idx)
+        : f(f_), g(g_), base_f(pop_at<QF>(idx, 0)), base_g(pop_at<QG>(idx, 0)) {}
+    __device__ void sf(int i, typename St::TF v) const { __builtin_nontemporal_store(v, f + base_f + i * kTile); }
+    __device__ void sg(int i, typename St::TG v) const { __builtin_nontemporal_store(v, g + base_g + i * kTile); }
+};
+
+template <class St> struct LdsDst {
+    typename St::TF* f;
+    typename St::TG* g;
+    uint32_t n, at;  // plane stride, local node index
+    __device__ void sf(int i, typename St::TF v) const { f[i * n + at] = v; }
+    __device__ void sg(int i, typename St::TG v) const { g[i * n + at] = v; }
+};
+
 // Returns false if the node's density or temperature is not finite.
-template <int DIM, class St>
+template <int DIM, class St, class Dst>
 __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R* hg,
-                                              const Coef<typename St::R>& c,
-                                              typename St::TF* __restrict__ fdst,
-                                              typename St::TG* __restrict__ gdst, uint32_t N,
-                                              uint32_t idx) {
+                                              const Coef<typename St::R>& c, const Dst& dst) {
     using R = typename St::R;
     using L = Flow<DIM>;
     using H = Heat<DIM>;
@@ -321,93 +338,231 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
     });
 
     // store post-collision populations at the node
-    const uint32_t base_f = pop_at<QF>(idx, 0), base_g = pop_at<QG>(idx, 0);
     static_for<0, QF>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        __builtin_nontemporal_store(St::EF::enc(hf[i]), fdst + base_f + i * kTile);
+        dst.sf(i, St::EF::enc(hf[i]));
     });
     static_for<0, QG>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        __builtin_nontemporal_store(St::EG::enc(hg[i]), gdst + base_g + i * kTile);
+        dst.sg(i, St::EG::enc(hg[i]));
     });
     return isfinite(drho + dT);
 }
 
 // ----------------------------------------------------------------- the step
-// One fused update of node idx: pull with the wall rules, moments, both
-// collisions, store.  Returns false if the new rho or T is not finite.
-template <int DIM, class St>
-__device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename St::R>& c,
-                                          const typename St::TF* __restrict__ fsrc,
-                                          const typename St::TG* __restrict__ gsrc,
-                                          typename St::TF* __restrict__ fdst,
-                                          typename St::TG* __restrict__ gdst, double* const* flux,
-                                          uint32_t idx) {
+// Sources of the pull.  at(sx, sy, sz) is the index of the node displaced by
+// (sx, sy, sz) in {-1, 0, 1}^3 from the current one; lf/lg read a
+// population plane there.  In global memory a displacement across a
+// periodic face wraps (the offsets are prepared per node); in an LDS tile
+// the halo already holds the wrapped neighbours.
+template <class St, int QF, int QG> struct GlobalSrc {
+    const typename St::TF* f;
+    const typename St::TG* g;
+    uint32_t idx;
+    int32_t oxm, oxp, oym, oyp, ozm, ozp;
+    __device__ uint32_t at(int sx, int sy, int sz) const {
+        return (uint32_t)((int32_t)idx + (sx < 0 ? oxm : sx > 0 ? oxp : 0) + (sy < 0 ? oym : sy > 0 ? oyp : 0) +
+                          (sz < 0 ? ozm : sz > 0 ? ozp : 0));
+    }
+    __device__ typename St::TF lf(int i, uint32_t node) const { return f[pop_at<QF>(node, i)]; }
+    __device__ typename St::TG lg(int i, uint32_t node) const { return g[pop_at<QG>(node, i)]; }
+};
+
+template <class St> struct LdsSrc {
+    const typename St::TF* f;
+    const typename St::TG* g;
+    uint32_t n;              // plane stride
+    int32_t at0, sy_stride;  // local node index, row stride
+    __device__ uint32_t at(int sx, int sy, int) const { return (uint32_t)(at0 + sx + sy * sy_stride); }
+    __device__ typename St::TF lf(int i, uint32_t node) const { return f[i * n + node]; }
+    __device__ typename St::TG lg(int i, uint32_t node) const { return g[i * n + node]; }
+};
+
+// Where a node's axis neighbours are: in the domain, across a periodic face
+// (wrapped), or beyond a wall.
+struct Neighbours {
+    bool okxm, okxp, okym, okyp, okzm, okzp;  // a neighbour exists on that side
+    bool inxm, inxp, inym, inyp, inzm, inzp;  // it is inside without wrapping
+};
+
+__device__ __forceinline__ Neighbours neighbours(const Geometry& g, uint32_t x, uint32_t y, uint32_t z) {
+    Neighbours n;
+    n.inxm = x > 0, n.inxp = x + 1 < g.nx;
+    n.inym = y > 0, n.inyp = y + 1 < g.ny;
+    n.inzm = z > 0, n.inzp = z + 1 < g.nz;
+    n.okxm = n.inxm || g.periodic[0], n.okxp = n.inxp || g.periodic[0];
+    n.okym = n.inym || g.periodic[1], n.okyp = n.inyp || g.periodic[1];
+    n.okzm = n.inzm || g.periodic[2], n.okzp = n.inzp || g.periodic[2];
+    return n;
+}
+
+template <class St, int QF, int QG>
+__device__ __forceinline__ GlobalSrc<St, QF, QG> global_src(const Geometry& g, const Neighbours& n,
+                                                            const typename St::TF* f, const typename St::TG* gp,
+                                                            uint32_t idx) {
+    const int32_t nx = (int32_t)g.nx, sy = nx, sz = nx * (int32_t)g.ny;
+    GlobalSrc<St, QF, QG> s;
+    s.f = f;
+    s.g = gp;
+    s.idx = idx;
+    s.oxm = n.inxm ? -1 : nx - 1;
+    s.oxp = n.inxp ? 1 : 1 - nx;
+    s.oym = n.inym ? -sy : ((int32_t)g.ny - 1) * sy;
+    s.oyp = n.inyp ? sy : -((int32_t)g.ny - 1) * sy;
+    s.ozm = n.inzm ? -sz : ((int32_t)g.nz - 1) * sz;
+    s.ozp = n.inzp ? sz : -((int32_t)g.nz - 1) * sz;
+    return s;
+}
+
+// One fused update of the node at (x, y, z): pull from `src` with the wall
+// rules, moments, both collisions, store to `dst`; the wall heat flux of
+// the node's Dirichlet links goes to `flux` when write_flux is set.
+// Returns false if the new rho or T is not finite.
+template <int DIM, class St, class Src, class Dst>
+__device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename St::R>& c, const Neighbours& nb,
+                                          uint32_t x, uint32_t y, uint32_t z, const Src& src, const Dst& dst,
+                                          double* const* flux, bool write_flux) {
     using R = typename St::R;
     using TF = typename St::TF;
     using L = Flow<DIM>;
     using H = Heat<DIM>;
-    uint32_t x, y, z;
-    coords(g, idx, x, y, z);
-
-    // pull offsets along each axis: a velocity with e_a = +1 pulls from
-    // coordinate c - 1 ("m"), e_a = -1 from c + 1 ("p")
-    const int32_t nx = (int32_t)g.nx, sy = nx, sz = nx * (int32_t)g.ny;
-    const bool inxm = x > 0, inxp = x + 1 < g.nx;
-    const bool inym = y > 0, inyp = y + 1 < g.ny;
-    const bool inzm = z > 0, inzp = z + 1 < g.nz;
-    const bool okxm = inxm || g.periodic[0], okxp = inxp || g.periodic[0];
-    const bool okym = inym || g.periodic[1], okyp = inyp || g.periodic[1];
-    const bool okzm = inzm || g.periodic[2], okzp = inzp || g.periodic[2];
-    const int32_t oxm = inxm ? -1 : nx - 1, oxp = inxp ? 1 : 1 - nx;
-    const int32_t oym = inym ? -sy : ((int32_t)g.ny - 1) * sy;
-    const int32_t oyp = inyp ? sy : -((int32_t)g.ny - 1) * sy;
-    const int32_t ozm = inzm ? -sz : ((int32_t)g.nz - 1) * sz;
-    const int32_t ozp = inzp ? sz : -((int32_t)g.nz - 1) * sz;
-
+    const uint32_t self = src.at(0, 0, 0);
     R hf[L::Q], hg[H::Q];
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
-        const bool out = (ex > 0 && !okxm) || (ex < 0 && !okxp) || (ey > 0 && !okym) ||
-                         (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
-        const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
-                            (ez > 0 ? ozm : ez < 0 ? ozp : 0);
-        TF v = fsrc[pop_at<L::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)];
-        if (out) v = fsrc[pop_at<L::Q>(idx, L::opp[i])];  // half-way bounce-back
+        const bool out = (ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
+                         (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp);
+        TF v = src.lf(i, out ? self : src.at(-ex, -ey, -ez));
+        if (out) v = src.lf(L::opp[i], self);  // half-way bounce-back
         hf[i] = St::EF::dec(v);
     });
     static_for<0, H::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ex = H::ex[i], ey = H::ey[i], ez = H::ez[i];
-        const bool out = (ex > 0 && !okxm) || (ex < 0 && !okxp) || (ey > 0 && !okym) ||
-                         (ey < 0 && !okyp) || (ez > 0 && !okzm) || (ez < 0 && !okzp);
-        const int32_t off = (ex > 0 ? oxm : ex < 0 ? oxp : 0) + (ey > 0 ? oym : ey < 0 ? oyp : 0) +
-                            (ez > 0 ? ozm : ez < 0 ? ozp : 0);
-        R r = St::EG::dec(gsrc[pop_at<H::Q>(out ? idx : (uint32_t)((int32_t)idx + off), i)]);
+        const bool out = (ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
+                         (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp);
+        R r = St::EG::dec(src.lg(i, out ? self : src.at(-ex, -ey, -ez)));
         if (out) {
             // the wall this link crosses: axis of e_i, the side it comes from
             constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
             constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
-            const R back = St::EG::dec(gsrc[pop_at<H::Q>(idx, H::opp[i])]);
+            const R back = St::EG::dec(src.lg(H::opp[i], self));
             if (g.dirichlet[face]) {
                 r = c.abb[face] - back;  // anti-bounce-back
-                const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
-                flux[face][local] = c.abb_d[face] - 2.0 * (double)back;
+                if (write_flux) {
+                    const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
+                    flux[face][local] = c.abb_d[face] - 2.0 * (double)back;
+                }
             } else {
                 r = back;  // adiabatic bounce-back
             }
         }
         hg[i] = r;
     });
-    return collide_store<DIM, St>(hf, hg, c, fdst, gdst, g.N, idx);
+    return collide_store<DIM, St>(hf, hg, c, dst);
+}
+
+// the update of node idx of the arrays fsrc/gsrc into fdst/gdst
+template <int DIM, class St>
+__device__ __forceinline__ bool step_node_global(const Geometry& g, const Coef<typename St::R>& c,
+                                                 const typename St::TF* fsrc, const typename St::TG* gsrc,
+                                                 typename St::TF* fdst, typename St::TG* gdst,
+                                                 double* const* flux, uint32_t idx) {
+    constexpr int QF = Flow<DIM>::Q, QG = Heat<DIM>::Q;
+    uint32_t x, y, z;
+    coords(g, idx, x, y, z);
+    const Neighbours nb = neighbours(g, x, y, z);
+    const auto src = global_src<St, QF, QG>(g, nb, fsrc, gsrc, idx);
+    const GlobalDst<St, QF, QG> dst(fdst, gdst, idx);
+    return step_node<DIM, St>(g, c, nb, x, y, z, src, dst, flux, true);
 }
 
 template <int DIM, class St>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
     const uint32_t idx = logical_block(a.geo.blocks_per_xcd) * kBlock + threadIdx.x;
     if (idx >= a.geo.N) return;
-    step_node<DIM, St>(a.geo, a.c, a.fsrc, a.gsrc, a.fdst, a.gdst, a.flux, idx);
+    step_node_global<DIM, St>(a.geo, a.c, a.fsrc, a.gsrc, a.fdst, a.gdst, a.flux, idx);
+}
+
+// ------------------------------------------------- two steps per launch (2D)
+// Temporal blocking: one block owns an output tile of kTile x TY nodes.
+// Step t+1 is computed for the tile and a ring of one node around it (the
+// region, RX x RY) from global memory into LDS, in the storage type, so the
+// values are exactly those a single step would have written; step t+2 is
+// then computed for the tile from LDS and written to global memory.  Global
+// traffic per node and two steps is one read and one write of the
+// populations instead of two of each.  Region nodes beyond a wall are
+// skipped (no tile node pulls from them: their links bounce back), region
+// nodes across a periodic face hold the wrapped node.
+template <class St> struct Step2Args {
+    const typename St::TF* fsrc;
+    const typename St::TG* gsrc;
+    typename St::TF* fdst;
+    typename St::TG* gdst;
+    double* flux1[6];  // wall heat flux of step t+1, per face
+    double* flux2[6];  // of step t+2
+    Geometry geo;
+    Coef<typename St::R> c;
+    uint32_t tiles_x, tiles;  // tiles per row, in all
+    uint32_t tiles_per_xcd;
+};
+
+// region coordinate -> domain coordinate, or -1 beyond a wall
+__device__ __forceinline__ int32_t region_coord(int32_t v, uint32_t n, int32_t periodic) {
+    if (v < 0) v = periodic ? v + (int32_t)n : -1;
+    else if (v >= (int32_t)n) v = periodic ? v - (int32_t)n : -1;
+    return v < (int32_t)n ? v : -1;
+}
+
+template <class St, int TY, int NW>
+__global__ __launch_bounds__(64 * NW) void step2_kernel(Step2Args<St> a) {
+    using TF = typename St::TF;
+    using TG = typename St::TG;
+    constexpr int QF = Flow<2>::Q, QG = Heat<2>::Q;
+    constexpr int TX = kTile, RX = TX + 2, RY = TY + 2, RN = RX * RY;
+    static_assert(2 * RY <= 64, "the halo columns must fit one wavefront");
+    __shared__ TF sf[QF * RN];
+    __shared__ TG sg[QG * RN];
+    const Geometry& g = a.geo;
+    const uint32_t tile = logical_block(a.tiles_per_xcd);
+    if (tile >= a.tiles) return;  // whole block
+    const int32_t x0 = (int32_t)((tile % a.tiles_x) * TX), y0 = (int32_t)((tile / a.tiles_x) * TY);
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+
+    // step t+1 on the region: RY rows of the kTile inner columns, then one
+    // unit of the two halo columns
+    for (int unit = wave; unit <= RY; unit += NW) {
+        int lx, ly;
+        if (unit < RY) {
+            lx = lane + 1, ly = unit;
+        } else {
+            if (lane >= 2 * RY) continue;
+            lx = (lane & 1) ? RX - 1 : 0, ly = lane >> 1;
+        }
+        const int32_t gx = region_coord(x0 - 1 + lx, g.nx, g.periodic[0]);
+        const int32_t gy = region_coord(y0 - 1 + ly, g.ny, g.periodic[1]);
+        if (gx < 0 || gy < 0) continue;
+        const uint32_t idx = (uint32_t)gx + g.nx * (uint32_t)gy;
+        const bool own = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && x0 - 1 + lx < (int32_t)g.nx &&
+                         y0 - 1 + ly < (int32_t)g.ny;
+        const Neighbours nb = neighbours(g, (uint32_t)gx, (uint32_t)gy, 0);
+        const auto src = global_src<St, QF, QG>(g, nb, a.fsrc, a.gsrc, idx);
+        const LdsDst<St> dst{sf, sg, (uint32_t)RN, (uint32_t)(ly * RX + lx)};
+        step_node<2, St>(g, a.c, nb, (uint32_t)gx, (uint32_t)gy, 0u, src, dst, a.flux1, own);
+    }
+    __syncthreads();
+
+    // step t+2 on the tile
+    for (int row = wave; row < TY; row += NW) {
+        const uint32_t x = (uint32_t)(x0 + lane), y = (uint32_t)(y0 + row);
+        if (x >= g.nx || y >= g.ny) continue;
+        const uint32_t idx = x + g.nx * y;
+        const Neighbours nb = neighbours(g, x, y, 0);
+        const LdsSrc<St> src{sf, sg, (uint32_t)RN, (row + 1) * RX + lane + 1, RX};
+        const GlobalDst<St, QF, QG> dst(a.fdst, a.gdst, idx);
+        step_node<2, St>(g, a.c, nb, x, y, 0u, src, dst, a.flux2, true);
+    }
 }
 
 // --------------------------------------------------------- batched cavities
@@ -441,8 +596,8 @@ __global__ __launch_bounds__(BS) void batch_step_kernel(BatchArgs<St> a) {
         const BatchCavity<St>& cv = a.cav[k];
         const uint32_t idx = (unit - cv.unit0) * BS + threadIdx.x;
         if (idx < cv.geo.N) {
-            const bool ok = step_node<DIM, St>(cv.geo, cv.c, cv.f[a.src], cv.g[a.src], cv.f[1 - a.src],
-                                               cv.g[1 - a.src], cv.flux[a.slot], idx);
+            const bool ok = step_node_global<DIM, St>(cv.geo, cv.c, cv.f[a.src], cv.g[a.src], cv.f[1 - a.src],
+                                                      cv.g[1 - a.src], cv.flux[a.slot], idx);
             if (!ok) a.unstable[k] = 1;
         }
     }
@@ -511,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs<St> a) {
         const double wt = i == 0 ? a.w_rest : a.w_move;
         hg[i] = (R)(wt * (T - tb) + 0.5 * eu * T);
     }
-    collide_store<DIM, St>(hf, hg, a.c, a.fdst, a.gdst, a.geo.N, idx);
+    collide_store<DIM, St>(hf, hg, a.c, GlobalDst<St, L::Q, H::Q>(a.fdst, a.gdst, idx));
 }
 
 // ----------------------------------------------------- moments of one node
@@ -665,6 +820,22 @@ __global__ __launch_bounds__(1024) void face_sum_kernel(FaceSumArgs a) {
         for (uint32_t i = threadIdx.x; i < a.count[b]; i += 1024) acc += a.buf[b][i];
     const double r = block_reduce<1024>(acc, AddOp{}, lds);
     if (threadIdx.x == 0) a.out[b] = r;
+}
+
+// Zeroes the unused lanes (nodes N .. end of tile) of the last storage tile
+// of a population array of Q planes of `elem`-byte values, so that a
+// checkpoint of the buffers depends on the state only.  One block.
+__global__ __launch_bounds__(kBlock) void clear_tail_kernel(unsigned char* p, uint32_t N, uint32_t Q,
+                                                            uint32_t elem) {
+    const uint32_t tile = N / kTile, first = N % kTile, plane_bytes = kTile * elem;
+    for (uint32_t k = threadIdx.x; k < Q * plane_bytes; k += kBlock) {
+        const uint32_t plane = k / plane_bytes, rem = k % plane_bytes;
+        if (rem / elem >= first) p[((size_t)tile * Q + plane) * plane_bytes + rem] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void zero_bytes_kernel(unsigned char* p, uint32_t n) {
+    for (uint32_t k = threadIdx.x; k < n; k += kBlock) p[k] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void fill_kernel(double* p, size_t n, double v) {

@@ -198,6 +198,7 @@ struct lbm_ctx {
     double t_base;
     int cond_axis;
     bool view;    // a cavity owned by a batch: the batch steps and initialises it
+    int32_t steps_per_launch;  // lbm_step: 1, or 2 (two-step tiles, 2D)
     char err[512];
 
     void* pop(int k) const { return ws + lay.off_pop[k]; }
@@ -353,6 +354,28 @@ lbm_status launch_init(lbm_ctx* c, int mode, uint32_t n0, uint32_t cnt, uint64_t
     });
 }
 
+// both population buffers: zero the bytes that hold no node (the lanes of
+// the last storage tile beyond N, the alignment gap after the f arrays)
+lbm_status clear_tails(lbm_ctx* c) {
+    const uint32_t N = c->geo.N;
+    const uint32_t qf = qf_of(c->p.dim), qg = qg_of(c->p.dim);
+    const uint32_t ef = (uint32_t)elem_f(c->p.storage), eg = (uint32_t)elem_g(c->p.storage);
+    const size_t f_used = (size_t)(N + kTile - 1) / kTile * kTile * qf * ef;
+    for (int k = 0; k < 2; ++k) {
+        unsigned char* base = (unsigned char*)c->pop(k);
+        if (N % kTile) {
+            hipLaunchKernelGGL(clear_tail_kernel, dim3(1), dim3(kBlock), 0, c->stream, base, N, qf, ef);
+            hipLaunchKernelGGL(clear_tail_kernel, dim3(1), dim3(kBlock), 0, c->stream, base + c->lay.f_bytes, N,
+                               qg, eg);
+        }
+        if (c->lay.f_bytes > f_used)
+            hipLaunchKernelGGL(zero_bytes_kernel, dim3(1), dim3(kBlock), 0, c->stream, base + f_used,
+                               (uint32_t)(c->lay.f_bytes - f_used));
+    }
+    HIP_TRY(c->err, hipGetLastError());
+    return LBM_OK;
+}
+
 lbm_status zero_flux(lbm_ctx* c) {
     const size_t n = 2 * c->lay.flux_doubles;
     if (n == 0) return LBM_OK;
@@ -382,6 +405,45 @@ lbm_status face_sums(lbm_ctx* c, double* host12) {
 }  // namespace
 
 // ======================================================================= ABI
+
+namespace {
+
+// Tile height of the two-step kernel: the region of (kTile + 2) x (TY + 2)
+// nodes of populations in LDS stays under ~77 KB, so two blocks share a CU.
+template <class St> constexpr int step2_rows() {
+    constexpr int bytes = Flow<2>::Q * (int)sizeof(typename St::TF) + Heat<2>::Q * (int)sizeof(typename St::TG);
+    constexpr int ry = 79000 / ((kTile + 2) * bytes);
+    return ry - 2 < 30 ? ry - 2 : 30;
+}
+constexpr int kStep2Waves = 4;
+
+// k launches of two steps each, A -> B, advancing t by 2k
+template <class St> void step2_launches(lbm_ctx* c, int64_t k) {
+    constexpr int TY = step2_rows<St>();
+    Step2Args<St> a{};
+    a.geo = c->geo;
+    a.c = make_coef<typename St::R>(c);
+    a.tiles_x = (c->geo.nx + kTile - 1) / kTile;
+    a.tiles = a.tiles_x * ((c->geo.ny + TY - 1) / TY);
+    a.tiles_per_xcd = (a.tiles + kXcd - 1) / kXcd;
+    const dim3 grid(a.tiles_per_xcd * kXcd), block(64 * kStep2Waves);
+    for (int64_t s = 0; s < k; ++s) {
+        const auto A = pops<St>(c, c->cur), B = pops<St>(c, 1 - c->cur);
+        a.fsrc = A.f;
+        a.gsrc = A.g;
+        a.fdst = B.f;
+        a.gdst = B.g;
+        for (int f = 0; f < 6; ++f) {
+            a.flux1[f] = c->flux((int)((c->t + 1) & 1), f);
+            a.flux2[f] = c->flux((int)((c->t + 2) & 1), f);
+        }
+        hipLaunchKernelGGL((step2_kernel<St, TY, kStep2Waves>), grid, block, 0, c->stream, a);
+        c->cur = 1 - c->cur;
+        c->t += 2;
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -439,6 +501,7 @@ lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void
     c->ws = (char*)d_workspace;
     c->cur = 0;
     c->t = -1;
+    c->steps_per_launch = p->dim == 2 && !view ? 2 : 1;
     Geometry& g = c->geo;
     g.nx = p->n[0];
     g.ny = p->n[1];
@@ -509,6 +572,7 @@ static lbm_status init_impl(lbm_ctx* c, uint64_t seed, double amp) {
     st = launch_init(c, 0, 0, c->geo.N, seed, amp, nullptr, nullptr, nullptr);
     if (st) return st;
     st = zero_flux(c);
+    if (!st) st = clear_tails(c);
     if (st) return st;
     c->t = 0;
     return LBM_OK;
@@ -534,6 +598,7 @@ static lbm_status init_fields_impl(lbm_ctx* c, const double* rho, const double* 
         HIP_TRY(c->err, hipStreamSynchronize(c->stream));
     }
     st = zero_flux(c);
+    if (!st) st = clear_tails(c);
     if (st) return st;
     HIP_TRY(c->err, hipStreamSynchronize(c->stream));
     c->t = 0;
@@ -550,6 +615,12 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     return dispatch(c, [&](auto dimc, auto stc) -> lbm_status {
         constexpr int DIM = decltype(dimc)::value;
         using St = decltype(stc);
+        if constexpr (DIM == 2) {
+            if (c->steps_per_launch == 2 && n >= 2) {
+                step2_launches<St>(c, n / 2);
+                n -= n / 2 * 2;
+            }
+        }
         StepArgs<St> a{};
         a.geo = c->geo;
         a.c = make_coef<typename St::R>(c);
@@ -570,6 +641,19 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         return LBM_OK;
     });
 }
+
+lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (c->view) return reject_view(c, "lbm_set_steps_per_launch");
+    if (steps != 1 && steps != 2) return set_err(c->err, LBM_E_INVALID, "steps per launch must be 1 or 2");
+    if (steps == 2 && c->p.dim != 2)
+        return set_err(c->err, LBM_E_UNSUPPORTED, "two steps per launch are implemented in 2D only");
+    c->steps_per_launch = steps;
+    return LBM_OK;
+}
+
+int32_t lbm_get_steps_per_launch(const lbm_ctx* c) { return c ? c->steps_per_launch : 0; }
 
 lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T) {
     lbm_status st = enter(c);

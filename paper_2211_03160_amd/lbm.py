@@ -26,6 +26,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_INVALID", -2: "LBM_E_DEVICE",
 # every entry point declared in include/lbm.h
 EXPORTS = ["lbm_derive", "lbm_workspace_bytes", "lbm_bytes_per_update",
            "lbm_create", "lbm_init", "lbm_init_fields", "lbm_step",
+           "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
            "lbm_fields", "lbm_nusselt", "lbm_wall_flux", "lbm_diagnostics",
            "lbm_state_bytes", "lbm_export_state", "lbm_import_state",
            "lbm_time", "lbm_destroy", "lbm_last_error", "lbm_lattice",
@@ -95,6 +96,9 @@ def lib():
         L.lbm_init.argtypes = [P, C.c_uint64, C.c_double]
         L.lbm_init_fields.argtypes = [P, dp, dp, dp]
         L.lbm_step.argtypes = [P, C.c_int64]
+        L.lbm_set_steps_per_launch.argtypes = [P, C.c_int32]
+        L.lbm_get_steps_per_launch.argtypes = [P]
+        L.lbm_get_steps_per_launch.restype = C.c_int32
         L.lbm_fields.argtypes = [P, P, P, P]
         L.lbm_nusselt.argtypes = [P, dp, dp]
         L.lbm_wall_flux.argtypes = [P, dp, dp]
@@ -137,7 +141,8 @@ def lib():
                      "lbm_batch_get_config"):
             getattr(L, name).restype = C.c_int32
         for name in ("lbm_derive", "lbm_create", "lbm_init", "lbm_init_fields",
-                     "lbm_step", "lbm_fields", "lbm_nusselt", "lbm_wall_flux",
+                     "lbm_step", "lbm_set_steps_per_launch", "lbm_fields",
+                     "lbm_nusselt", "lbm_wall_flux",
                      "lbm_diagnostics", "lbm_export_state", "lbm_import_state",
                      "lbm_lattice"):
             getattr(L, name).restype = C.c_int32
@@ -262,6 +267,15 @@ class Cavity:
         self._check(lib().lbm_step(self._h, int(n)))
 
     @property
+    def steps_per_launch(self) -> int:
+        """Steps per kernel launch of step(): 1, or 2 (2D, the default)."""
+        return int(lib().lbm_get_steps_per_launch(self._h))
+
+    @steps_per_launch.setter
+    def steps_per_launch(self, k: int):
+        self._check(lib().lbm_set_steps_per_launch(self._h, int(k)))
+
+    @property
     def t(self) -> int:
         return int(lib().lbm_time(self._h))
 
@@ -319,7 +333,9 @@ class Cavity:
         return derive(self.cfg)
 
     def bytes_per_update(self) -> float:
-        return bytes_per_update(self.cfg)
+        """Algorithmic HBM bytes per lattice update at the current number
+        of steps per launch."""
+        return bytes_per_update(self.cfg) / self.steps_per_launch
 
 
 class _View(Cavity):

@@ -1,0 +1,80 @@
+"""Two steps per launch (2D temporal blocking) against one step per launch.
+
+The two-step kernel applies the same per-node update to the same stored
+values (the intermediate state goes through LDS in the storage type), so the
+whole exported state -- populations, both wall-flux slots and t -- must be
+bitwise identical, in every storage mode and boundary layout, including
+grids smaller than one tile, ragged tiles and an odd step count (which ends
+with a single-step launch).  Parity of the default (two-step) path with the
+oracle is covered by test_gpu_parity."""
+import numpy as np
+import pytest
+
+from paper_2211_03160_amd import lbm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STORAGES = ["fp32", "fp64", "fp16", "bf16", "mixed"]
+SHAPES = [(129, 129), (67, 45), (64, 19), (65, 20), (5, 7), (2, 2), (300, 3), (7, 200), (1, 33), (40, 1)]
+
+
+def _layouts(shape, storage):
+    return {
+        "rb": W.rayleigh_benard(2, shape, ra=5e4, pr=0.71, storage=storage),
+        "side": W.side_heated(2, shape, ra=5e4, pr=0.71, storage=storage),
+        "box": W.periodic_box(2, shape, nu=0.02, alpha=0.03, gbeta=1e-4, storage=storage),
+    }
+
+
+def _run(cfg, spl, steps, seed=9, amp=2e-2):
+    c = lbm.Cavity(cfg)
+    c.steps_per_launch = spl
+    assert c.steps_per_launch == spl
+    c.init(seed, amp)
+    c.step(steps)
+    return c
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_two_step_bitwise(storage, shape):
+    for name, cfg in _layouts(shape, storage).items():
+        if name != "box" and min(shape) < 2:
+            continue  # a walled axis needs two nodes
+        one = _run(cfg, 1, 23)
+        two = _run(cfg, 2, 23)
+        assert one.t == two.t == 23
+        a, b = one.export_state(), two.export_state()
+        assert len(a) == len(b)
+        if a != b:
+            x, y = np.frombuffer(a, np.uint8), np.frombuffer(b, np.uint8)
+            bad = np.flatnonzero(x != y)
+            pytest.fail(f"{name} {shape} {storage}: {bad.size} bytes differ, first at {bad[:8]}")
+
+
+def test_two_step_after_single_steps_and_nusselt():
+    """Mixing launch modes mid-run keeps the state and the flux history."""
+    cfg = W.rayleigh_benard(2, (257, 129), ra=1e5, pr=0.71, storage="fp32")
+    ref = _run(cfg, 1, 0)
+    mix = _run(cfg, 1, 0)
+    for n in (3, 4, 1, 6, 5):
+        ref.step(n)
+        mix.steps_per_launch = 2 if mix.steps_per_launch == 1 else 1
+        mix.step(n)
+    assert ref.export_state() == mix.export_state()
+    assert ref.nusselt() == mix.nusselt()
+
+
+def test_steps_per_launch_arguments():
+    c2 = lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage="fp32"))
+    assert c2.steps_per_launch == 2
+    for bad in (0, 3, -1):
+        with pytest.raises(lbm.LBMError) as e:
+            c2.steps_per_launch = bad
+        assert e.value.status == -1
+    c3 = lbm.Cavity(W.rayleigh_benard(3, (9, 9, 9), ra=1e4, pr=0.71, storage="fp32"))
+    assert c3.steps_per_launch == 1
+    with pytest.raises(lbm.LBMError) as e:
+        c3.steps_per_launch = 2
+    assert e.value.status == -5
+    c3.steps_per_launch = 1
