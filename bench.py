@@ -247,7 +247,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic,
-                "kernel": "lbm::step2_kernel<StF32, 19, 4>" if spl == 2 else "lbm::step_kernel<2, StF32>",
+                "kernel": "lbm::stream2_kernel<StF32, 4, true>" if spl == 2 else "lbm::step_kernel<2, StF32>",
                 "steps_per_launch": spl,
                 "launch_ms": round(launch_s * 1e3, 4),
                 "bytes_per_node_per_launch": bpu * spl,

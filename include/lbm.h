@@ -171,12 +171,13 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
 /* Steps per kernel launch of lbm_step: 1, or 2 (2D only; the default in
- * 2D).  With 2, each launch computes step t+1 for a tile of nodes and its
- * one-node ring into on-chip memory and step t+2 of the tile from there:
- * the update of every node is the same arithmetic on the same stored
- * values as with 1, so the results are bitwise identical; only the global
- * memory traffic per step halves.  LBM_E_INVALID for other values,
- * LBM_E_UNSUPPORTED for 2 in 3D, LBM_E_STATE for a batch member.       */
+ * 2D).  With 2, each wavefront walks down a strip of columns row by row,
+ * keeping the last rows of step t and of step t+1 in registers, and
+ * writes step t+2: the update of every node is the same arithmetic on the
+ * same stored values as with 1, so the results are bitwise identical;
+ * only the global memory traffic per step halves.  LBM_E_INVALID for
+ * other values, LBM_E_UNSUPPORTED for 2 in 3D, LBM_E_STATE for a batch
+ * member.                                                               */
 lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps);
 int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
 

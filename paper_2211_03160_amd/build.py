@@ -15,8 +15,12 @@ LIB = os.path.join(LIB_DIR, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "nn_api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# -ffp-contract=on: a multiply is fused with an add only inside one source
+# expression, never across statements, so the same update rounds the same
+# way wherever it is inlined (the single-step and the two-step kernels must
+# agree bit for bit).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         "-Wall", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
 

@@ -108,10 +108,12 @@ struct Geometry {
     uint32_t blocks_per_xcd;  // logical blocks handled by each XCD
 };
 
+// Relaxation rates are indexed by row kind (RowKind), not by row: rows of
+// one kind share a rate, so a kernel holds only the distinct values.
 template <class R> struct Coef {
-    R s[19];     // flow rate per moment row (0 on conserved rows)
-    R b[19];     // 1 - s/2 per row
-    R q[7];      // thermal rate per row
+    R s[10];     // flow rate per row kind (0 on conserved kinds)
+    R b[10];     // 1 - s/2 per row kind
+    R q[10];     // thermal rate per row kind
     R a_t;       // thermal equilibrium constant a_T
     R gbeta;     // g beta
     R t_base;    // T_b
@@ -233,25 +235,38 @@ __device__ __forceinline__ R force_mom(int k, const R* u, const R* F) {
 
 // Moments, both collisions and the store of one node.  hf/hg hold the
 // pre-collision deviations on entry.
+// Element i of array p.  With O32 the byte offset is formed in 32 bits
+// (valid for arrays under 4 GiB), which lets the load or store take the
+// array base from scalar registers and the offset from one vector register.
+template <bool O32, class T> __device__ __forceinline__ T* elem(T* p, uint32_t i) {
+    if constexpr (O32) return (T*)((char*)p + i * (uint32_t)sizeof(T));
+    else return p + i;
+}
+template <bool O32, class T> __device__ __forceinline__ const T* elem(const T* p, uint32_t i) {
+    if constexpr (O32) return (const T*)((const char*)p + i * (uint32_t)sizeof(T));
+    else return p + i;
+}
+
 // Destinations of the post-collision populations of one node: the tiled
-// arrays in global memory (non-temporal stores) or a tile in LDS.
-template <class St, int QF, int QG> struct GlobalDst {
+// arrays in global memory.
+// NT: non-temporal stores (a one-pass kernel whose waves end after their
+// stores); plain stores for kernels that keep loading after storing.
+template <class St, int QF, int QG, bool O32 = false, bool NT = true> struct GlobalDst {
     typename St::TF* f;
     typename St::TG* g;
     uint32_t base_f, base_g;
     __device__ GlobalDst(typename St::TF* f_, typename St::TG* g_, uint32_t idx)
         : f(f_), g(g_), base_f(pop_at<QF>(idx, 0)), base_g(pop_at<QG>(idx, 0)) {}
-    __device__ void sf(int i, typename St::TF v) const { __builtin_nontemporal_store(v, f + base_f + i * kTile); }
-    __device__ void sg(int i, typename St::TG v) const { __builtin_nontemporal_store(v, g + base_g + i * kTile); }
+    __device__ void sf(int i, typename St::TF v) const {
+        if constexpr (NT) __builtin_nontemporal_store(v, elem<O32>(f, base_f + i * kTile));
+        else *elem<O32>(f, base_f + i * kTile) = v;
+    }
+    __device__ void sg(int i, typename St::TG v) const {
+        if constexpr (NT) __builtin_nontemporal_store(v, elem<O32>(g, base_g + i * kTile));
+        else *elem<O32>(g, base_g + i * kTile) = v;
+    }
 };
 
-template <class St> struct LdsDst {
-    typename St::TF* f;
-    typename St::TG* g;
-    uint32_t n, at;  // plane stride, local node index
-    __device__ void sf(int i, typename St::TF v) const { f[i * n + at] = v; }
-    __device__ void sg(int i, typename St::TG v) const { g[i * n + at] = v; }
-};
 
 // Returns false if the node's density or temperature is not finite.
 template <int DIM, class St, class Dst>
@@ -296,7 +311,7 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
                 constexpr int i = decltype(ic)::value;
                 cmac<L::M(k, i)>(mk, hf[i]);
             });
-            d = -c.s[k] * (mk - eq_dev<DIM>(k, rho, drho, u)) + c.b[k] * force_mom<DIM>(k, u, F);
+            d = -c.s[kind] * (mk - eq_dev<DIM>(k, rho, drho, u)) + c.b[kind] * force_mom<DIM>(k, u, F);
         }
         dm[k] = d * R(1.0 / row_norm<L>(k));
     });
@@ -322,9 +337,9 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
         });
         R d;
         if constexpr (kind == kRho) d = R(0);
-        else if constexpr (kind == kJx || kind == kJy || kind == kJz) d = -c.q[k] * (nk - u[kind - kJx] * T);
-        else if constexpr (kind == kE) d = -c.q[k] * (nk - c.a_t * dT);
-        else d = -c.q[k] * nk;
+        else if constexpr (kind == kJx || kind == kJy || kind == kJz) d = -c.q[kind] * (nk - u[kind - kJx] * T);
+        else if constexpr (kind == kE) d = -c.q[kind] * (nk - c.a_t * dT);
+        else d = -c.q[kind] * nk;
         dn[k] = d * R(1.0 / row_norm<H>(k));
     });
     static_for<0, QG>([&](auto ic) {
@@ -349,13 +364,70 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
     return isfinite(drho + dT);
 }
 
+// --------------------------------------------------------- store helpers
+// Raw buffer stores.  A lane whose byte offset is at or beyond the buffer
+// size stores nothing (the hardware drops out-of-range buffer writes), so a
+// store masked this way needs no branch: every lane executes it.  Offsets
+// stay below 2^32 for buffers under 4 GiB - 4 KiB, with any immediate offset
+// the compiler folds in.
+constexpr uint32_t kBufferWord3 = 0x00020000u;  // gfx9 raw buffer, 32-bit data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, (int)kBufferWord3);
+}
+
+template <class T>
+__device__ __forceinline__ void buffer_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t offset) {
+    if constexpr (sizeof(T) == 2) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(short, v), r, (int)offset, 0, 0);
+    } else if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)offset, 0, 0);
+    } else {
+        using I2 = int __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(I2, v), r, (int)offset, 0, 0);
+    }
+}
+
+// Wall heat flux sinks: put<face>(g, local, value, wall) records the value
+// of a link that crosses a Dirichlet wall (wall true) at index `local` of
+// that face.
+struct NoFlux {
+    template <int face> __device__ void put(const Geometry&, uint32_t, double, bool) const {}
+};
+
+struct PtrFlux {  // per-face arrays
+    double* const* flux;
+    bool on;
+    template <int face> __device__ void put(const Geometry&, uint32_t local, double v, bool wall) const {
+        if (on && wall) flux[face][local] = v;
+    }
+};
+
+// the faces of one slot back to back (face f starts after the node counts
+// of faces 0 .. f-1) in a buffer; writes with dropped lanes, no branch (2D)
+struct BufFlux2 {
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t slot;  // first element of the slot
+    uint32_t drop;  // byte offset beyond the buffer
+    bool on;
+    template <int face> __device__ void put(const Geometry& g, uint32_t local, double v, bool wall) const {
+        const uint32_t start = face == 0 ? 0u : face == 1 ? g.ny : face == 2 ? 2u * g.ny : 2u * g.ny + g.nx;
+        buffer_store(v, r, on && wall ? (slot + start + local) * 8u : drop);
+    }
+};
+
 // ----------------------------------------------------------------- the step
-// Sources of the pull.  at(sx, sy, sz) is the index of the node displaced by
+// Sources of the pull.  pull_f<i, ex, ey, ez, o>(out) returns the decoded
+// population f_i arriving at the node along e_i = (ex, ey, ez): from the
+// neighbour at -e_i, or, when that link crosses a wall (out), the opposite
+// population o at the node itself (bounce-back); pull_g likewise for g.
+//
+// GlobalSrc: the tiled arrays in global memory.  at(sx, sy, sz) is the index of the node displaced by
 // (sx, sy, sz) in {-1, 0, 1}^3 from the current one; lf/lg read a
 // population plane there.  In global memory a displacement across a
 // periodic face wraps (the offsets are prepared per node); in an LDS tile
 // the halo already holds the wrapped neighbours.
-template <class St, int QF, int QG> struct GlobalSrc {
+template <class St, int QF, int QG, bool O32 = false> struct GlobalSrc {
     const typename St::TF* f;
     const typename St::TG* g;
     uint32_t idx;
@@ -364,19 +436,17 @@ template <class St, int QF, int QG> struct GlobalSrc {
         return (uint32_t)((int32_t)idx + (sx < 0 ? oxm : sx > 0 ? oxp : 0) + (sy < 0 ? oym : sy > 0 ? oyp : 0) +
                           (sz < 0 ? ozm : sz > 0 ? ozp : 0));
     }
-    __device__ typename St::TF lf(int i, uint32_t node) const { return f[pop_at<QF>(node, i)]; }
-    __device__ typename St::TG lg(int i, uint32_t node) const { return g[pop_at<QG>(node, i)]; }
+    __device__ typename St::TF lf(int i, uint32_t node) const { return *elem<O32>(f, pop_at<QF>(node, i)); }
+    __device__ typename St::TG lg(int i, uint32_t node) const { return *elem<O32>(g, pop_at<QG>(node, i)); }
+    // both cases from one node index and one plane: a single load serves either
+    template <int i, int ex, int ey, int ez, int o> __device__ typename St::R pull_f(bool out) const {
+        return St::EF::dec(lf(out ? o : i, out ? at(0, 0, 0) : at(-ex, -ey, -ez)));
+    }
+    template <int i, int ex, int ey, int ez, int o> __device__ typename St::R pull_g(bool out) const {
+        return St::EG::dec(lg(out ? o : i, out ? at(0, 0, 0) : at(-ex, -ey, -ez)));
+    }
 };
 
-template <class St> struct LdsSrc {
-    const typename St::TF* f;
-    const typename St::TG* g;
-    uint32_t n;              // plane stride
-    int32_t at0, sy_stride;  // local node index, row stride
-    __device__ uint32_t at(int sx, int sy, int) const { return (uint32_t)(at0 + sx + sy * sy_stride); }
-    __device__ typename St::TF lf(int i, uint32_t node) const { return f[i * n + node]; }
-    __device__ typename St::TG lg(int i, uint32_t node) const { return g[i * n + node]; }
-};
 
 // Where a node's axis neighbours are: in the domain, across a periodic face
 // (wrapped), or beyond a wall.
@@ -396,12 +466,12 @@ __device__ __forceinline__ Neighbours neighbours(const Geometry& g, uint32_t x, 
     return n;
 }
 
-template <class St, int QF, int QG>
-__device__ __forceinline__ GlobalSrc<St, QF, QG> global_src(const Geometry& g, const Neighbours& n,
-                                                            const typename St::TF* f, const typename St::TG* gp,
-                                                            uint32_t idx) {
+template <class St, int QF, int QG, bool O32 = false>
+__device__ __forceinline__ GlobalSrc<St, QF, QG, O32> global_src(const Geometry& g, const Neighbours& n,
+                                                                 const typename St::TF* f,
+                                                                 const typename St::TG* gp, uint32_t idx) {
     const int32_t nx = (int32_t)g.nx, sy = nx, sz = nx * (int32_t)g.ny;
-    GlobalSrc<St, QF, QG> s;
+    GlobalSrc<St, QF, QG, O32> s;
     s.f = f;
     s.g = gp;
     s.idx = idx;
@@ -416,49 +486,51 @@ __device__ __forceinline__ GlobalSrc<St, QF, QG> global_src(const Geometry& g, c
 
 // One fused update of the node at (x, y, z): pull from `src` with the wall
 // rules, moments, both collisions, store to `dst`; the wall heat flux of
-// the node's Dirichlet links goes to `flux` when write_flux is set.
+// the node's Dirichlet links goes to the flux sink `fx`.
 // Returns false if the new rho or T is not finite.
-template <int DIM, class St, class Src, class Dst>
+template <int DIM, class St, class Src, class Dst, class Flux>
 __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename St::R>& c, const Neighbours& nb,
                                           uint32_t x, uint32_t y, uint32_t z, const Src& src, const Dst& dst,
-                                          double* const* flux, bool write_flux) {
+                                          const Flux& fx) {
     using R = typename St::R;
-    using TF = typename St::TF;
     using L = Flow<DIM>;
     using H = Heat<DIM>;
-    const uint32_t self = src.at(0, 0, 0);
     R hf[L::Q], hg[H::Q];
+    // The gather is free of branches: a link that crosses a wall reads the
+    // opposite plane at the node itself (bounce-back) through the same
+    // single load, so every load is issued before any result is waited
+    // for; the wall heat fluxes are stored after the gather.
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
         const bool out = (ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
                          (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp);
-        TF v = src.lf(i, out ? self : src.at(-ex, -ey, -ez));
-        if (out) v = src.lf(L::opp[i], self);  // half-way bounce-back
-        hf[i] = St::EF::dec(v);
+        hf[i] = src.template pull_f<i, ex, ey, ez, L::opp[i]>(out);
     });
+    R wall_v[H::Q];
+    bool wall_abb[H::Q];
     static_for<0, H::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ex = H::ex[i], ey = H::ey[i], ez = H::ez[i];
+        // the wall a crossing link meets: axis of e_i, the side it comes from
+        constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
+        constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
         const bool out = (ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
                          (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp);
-        R r = St::EG::dec(src.lg(i, out ? self : src.at(-ex, -ey, -ez)));
-        if (out) {
-            // the wall this link crosses: axis of e_i, the side it comes from
-            constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
-            constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
-            const R back = St::EG::dec(src.lg(H::opp[i], self));
-            if (g.dirichlet[face]) {
-                r = c.abb[face] - back;  // anti-bounce-back
-                if (write_flux) {
-                    const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
-                    flux[face][local] = c.abb_d[face] - 2.0 * (double)back;
-                }
-            } else {
-                r = back;  // adiabatic bounce-back
-            }
-        }
-        hg[i] = r;
+        const R v = src.template pull_g<i, ex, ey, ez, H::opp[i]>(out);
+        // anti-bounce-back on a Dirichlet wall, plain bounce-back (adiabatic)
+        // otherwise
+        wall_abb[i] = i != 0 && out && g.dirichlet[face];
+        wall_v[i] = v;
+        hg[i] = wall_abb[i] ? c.abb[face] - v : v;
+    });
+    static_for<1, H::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ex = H::ex[i], ey = H::ey[i], ez = H::ez[i];
+        constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
+        constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
+        const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
+        fx.template put<face>(g, local, c.abb_d[face] - 2.0 * (double)wall_v[i], wall_abb[i]);
     });
     return collide_store<DIM, St>(hf, hg, c, dst);
 }
@@ -475,7 +547,7 @@ __device__ __forceinline__ bool step_node_global(const Geometry& g, const Coef<t
     const Neighbours nb = neighbours(g, x, y, z);
     const auto src = global_src<St, QF, QG>(g, nb, fsrc, gsrc, idx);
     const GlobalDst<St, QF, QG> dst(fdst, gdst, idx);
-    return step_node<DIM, St>(g, c, nb, x, y, z, src, dst, flux, true);
+    return step_node<DIM, St>(g, c, nb, x, y, z, src, dst, PtrFlux{flux, true});
 }
 
 template <int DIM, class St>
@@ -485,83 +557,227 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs<St> a) {
     step_node_global<DIM, St>(a.geo, a.c, a.fsrc, a.gsrc, a.fdst, a.gdst, a.flux, idx);
 }
 
-// ------------------------------------------------- two steps per launch (2D)
-// Temporal blocking: one block owns an output tile of kTile x TY nodes.
-// Step t+1 is computed for the tile and a ring of one node around it (the
-// region, RX x RY) from global memory into LDS, in the storage type, so the
-// values are exactly those a single step would have written; step t+2 is
-// then computed for the tile from LDS and written to global memory.  Global
-// traffic per node and two steps is one read and one write of the
-// populations instead of two of each.  Region nodes beyond a wall are
-// skipped (no tile node pulls from them: their links bounce back), region
-// nodes across a periodic face hold the wrapped node.
-template <class St> struct Step2Args {
+// coordinate v along an axis of n nodes -> domain coordinate: wrapped on a
+// periodic axis (any number of times: a region can be wider than the
+// domain), -1 beyond a wall
+__device__ __forceinline__ int32_t region_coord(int32_t v, uint32_t n, int32_t periodic) {
+    if (v >= 0 && v < (int32_t)n) return v;
+    if (!periodic) return -1;
+    const int32_t r = v % (int32_t)n;
+    return r < 0 ? r + (int32_t)n : r;
+}
+
+// ------------------------------------- two steps per launch, register rows
+// A wavefront walks down a strip of kStripCols columns, one row per
+// iteration.  Lane l holds column x0 - 2 + l.  The last rows of the input
+// state and of step t+1 stay in registers as decoded values (rounded through
+// the storage type, so exactly what a single step would store and reload);
+// the x-neighbours of a lane come from its neighbour lanes by DPP wave
+// shifts.  Step t+1 is valid on lanes 1..62, step t+2 on lanes 2..61, which
+// are the strip's own columns.  Row iteration k loads input row y0 - 2 + k,
+// computes step t+2 on row y0 - 6 + k and step t+1 on row y0 - 4 + k: a
+// row's loads are issued one whole iteration before their first use, so
+// every wavefront keeps a row of loads in flight while it computes.
+constexpr int kStripCols = 60;
+
+// the value of v held by lane l - 1 (FromLeft) or lane l + 1 (otherwise)
+template <bool FromLeft> __device__ __forceinline__ float lane_shift(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                  FromLeft ? 0x138 : 0x130, 0xf, 0xf, false));
+}
+template <bool FromLeft> __device__ __forceinline__ double lane_shift(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, FromLeft ? 0x138 : 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), FromLeft ? 0x138 : 0x130, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// pull source: three register rows (y - 1, y, y + 1) of decoded populations
+template <class St, int QF, int QG> struct RegSrc {
+    using R = typename St::R;
+    const R (&fm)[QF];
+    const R (&fz)[QF];
+    const R (&fp)[QF];
+    const R (&gm)[QG];
+    const R (&gz)[QG];
+    const R (&gp)[QG];
+    template <int ex, int ey, class A> __device__ static R from(const A& m, const A& z, const A& p, int i) {
+        R v = ey > 0 ? m[i] : ey < 0 ? p[i] : z[i];
+        if constexpr (ex > 0) v = lane_shift<true>(v);
+        else if constexpr (ex < 0) v = lane_shift<false>(v);
+        return v;
+    }
+    template <int i, int ex, int ey, int ez, int o> __device__ R pull_f(bool out) const {
+        const R v = from<ex, ey>(fm, fz, fp, i);
+        return out ? fz[o] : v;
+    }
+    template <int i, int ex, int ey, int ez, int o> __device__ R pull_g(bool out) const {
+        const R v = from<ex, ey>(gm, gz, gp, i);
+        return out ? gz[o] : v;
+    }
+};
+
+// store into a register row, decoded (the value the next step reads)
+template <class St, int QF, int QG> struct RegDst {
+    typename St::R (&f)[QF];
+    typename St::R (&g)[QG];
+    __device__ void sf(int i, typename St::TF v) const { f[i] = St::EF::dec(v); }
+    __device__ void sg(int i, typename St::TG v) const { g[i] = St::EG::dec(v); }
+};
+
+// Global stores for the lanes that own their node.  Stores and loads
+// retire through one in-order counter, and a store under a branch leaves
+// the compiler unsure it was issued, so it then waits for more of the
+// memory operations after a load than the load needs; the buffer form
+// drops the other lanes' stores instead and keeps the code straight-line.
+template <class St, int QF, int QG> struct OwnedBufDst {
+    __amdgpu_buffer_rsrc_t rf, rg;
+    uint32_t of, og;  // byte offset of the node's first plane, or beyond the buffer
+    __device__ OwnedBufDst(__amdgpu_buffer_rsrc_t rf_, __amdgpu_buffer_rsrc_t rg_, uint32_t f_bytes,
+                           uint32_t g_bytes, uint32_t idx, bool own)
+        : rf(rf_), rg(rg_),
+          of(own ? pop_at<QF>(idx, 0) * (uint32_t)sizeof(typename St::TF) : f_bytes),
+          og(own ? pop_at<QG>(idx, 0) * (uint32_t)sizeof(typename St::TG) : g_bytes) {}
+    __device__ void sf(int i, typename St::TF v) const {
+        buffer_store(v, rf, of + (uint32_t)(i * kTile * sizeof(typename St::TF)));
+    }
+    __device__ void sg(int i, typename St::TG v) const {
+        buffer_store(v, rg, og + (uint32_t)(i * kTile * sizeof(typename St::TG)));
+    }
+};
+
+// the same for arrays of 4 GiB or more: branches around plain stores
+template <class St, int QF, int QG> struct OwnedGlobalDst : GlobalDst<St, QF, QG, false, false> {
+    bool own;
+    __device__ OwnedGlobalDst(typename St::TF* f_, typename St::TG* g_, uint32_t idx, bool own_)
+        : GlobalDst<St, QF, QG, false, false>(f_, g_, idx), own(own_) {}
+    __device__ void sf(int i, typename St::TF v) const {
+        if (own) GlobalDst<St, QF, QG, false, false>::sf(i, v);
+    }
+    __device__ void sg(int i, typename St::TG v) const {
+        if (own) GlobalDst<St, QF, QG, false, false>::sg(i, v);
+    }
+};
+
+// flux slot in one array, faces back to back (2D), plain stores under a branch
+struct PtrFlux2 {
+    double* base;
+    uint32_t slot;
+    bool on;
+    template <int face> __device__ void put(const Geometry& g, uint32_t local, double v, bool wall) const {
+        const uint32_t start = face == 0 ? 0u : face == 1 ? g.ny : face == 2 ? 2u * g.ny : 2u * g.ny + g.nx;
+        if (on && wall) base[slot + start + local] = v;
+    }
+};
+
+template <class St> struct Stream2Args {
     const typename St::TF* fsrc;
     const typename St::TG* gsrc;
     typename St::TF* fdst;
     typename St::TG* gdst;
-    double* flux1[6];  // wall heat flux of step t+1, per face
-    double* flux2[6];  // of step t+2
+    double* flux;                     // wall heat flux area: two slots, faces back to back
+    uint32_t f_bytes, g_bytes;        // sizes of fdst, gdst (buffer stores)
+    uint32_t flux_bytes;              // size of the flux area
+    uint32_t slot1, slot2;            // first element of the slots of steps t+1, t+2
     Geometry geo;
     Coef<typename St::R> c;
-    uint32_t tiles_x, tiles;  // tiles per row, in all
-    uint32_t tiles_per_xcd;
+    uint32_t strips;          // strips across x
+    uint32_t seg_rows;        // rows per strip segment
+    uint32_t units;           // strips x segments, one per wavefront
+    uint32_t blocks_per_xcd;
 };
 
-// region coordinate -> domain coordinate, or -1 beyond a wall
-__device__ __forceinline__ int32_t region_coord(int32_t v, uint32_t n, int32_t periodic) {
-    if (v < 0) v = periodic ? v + (int32_t)n : -1;
-    else if (v >= (int32_t)n) v = periodic ? v - (int32_t)n : -1;
-    return v < (int32_t)n ? v : -1;
-}
+// Register budget: four wavefronts per SIMD (128 registers) with FP32
+// arithmetic, two with FP64, whose rows take twice the registers.
+template <class St> constexpr int stream_waves_per_simd() { return sizeof(typename St::R) == 8 ? 2 : 4; }
 
-template <class St, int TY, int NW>
-__global__ __launch_bounds__(64 * NW) void step2_kernel(Step2Args<St> a) {
-    using TF = typename St::TF;
-    using TG = typename St::TG;
+template <class St, int NWB, bool O32>
+__global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St>())))
+void stream2_kernel(Stream2Args<St> a) {
+    using R = typename St::R;
     constexpr int QF = Flow<2>::Q, QG = Heat<2>::Q;
-    constexpr int TX = kTile, RX = TX + 2, RY = TY + 2, RN = RX * RY;
-    static_assert(2 * RY <= 64, "the halo columns must fit one wavefront");
-    __shared__ TF sf[QF * RN];
-    __shared__ TG sg[QG * RN];
     const Geometry& g = a.geo;
-    const uint32_t tile = logical_block(a.tiles_per_xcd);
-    if (tile >= a.tiles) return;  // whole block
-    const int32_t x0 = (int32_t)((tile % a.tiles_x) * TX), y0 = (int32_t)((tile / a.tiles_x) * TY);
-    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t unit = logical_block(a.blocks_per_xcd) * NWB + wave;
+    if (unit >= a.units) return;  // whole wavefront
+    const int32_t x0 = (int32_t)((unit % a.strips) * kStripCols);
+    const int32_t y0 = (int32_t)((unit / a.strips) * a.seg_rows);
+    const int32_t rows = min((int32_t)a.seg_rows, (int32_t)g.ny - y0);
+    const int32_t cx = x0 - 2 + lane;                       // this lane's column, unwrapped
+    const int32_t col = region_coord(cx, g.nx, g.periodic[0]);  // -1 beyond a wall
+    const uint32_t ucol = col < 0 ? 0u : (uint32_t)col;     // any in-domain column for dead lanes
+    const bool own_col = lane >= 2 && lane < 2 + kStripCols && cx < (int32_t)g.nx;
 
-    // step t+1 on the region: RY rows of the kTile inner columns, then one
-    // unit of the two halo columns
-    for (int unit = wave; unit <= RY; unit += NW) {
-        int lx, ly;
-        if (unit < RY) {
-            lx = lane + 1, ly = unit;
-        } else {
-            if (lane >= 2 * RY) continue;
-            lx = (lane & 1) ? RX - 1 : 0, ly = lane >> 1;
+    // rows a step never fills (beyond a wall) are only ever discarded by the
+    // bounce-back selects; start them at zero so no value is indeterminate
+    R fin[4][QF] = {}, gin[4][QG] = {};  // input rows, ring of four
+    R f1[4][QF] = {}, g1[4][QG] = {};    // step t+1 rows, ring of four
+
+    // The loop body is straight-line: every iteration loads a row and
+    // computes both steps; rows outside the segment or beyond a wall use an
+    // in-domain stand-in row and are never stored.  (Branches around the
+    // loads would leave paths on which a load is not waited for, after which
+    // the compiler drains every outstanding load before the next row.)
+    const int32_t last = (int32_t)g.ny - 1;
+    const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
+    const __amdgpu_buffer_rsrc_t rflux = buffer_rsrc(a.flux, a.flux_bytes);
+    auto iteration = [&](auto slot, int32_t k) {
+        constexpr int S = decltype(slot)::value;  // k mod 4
+        constexpr int A = (S + 1) % 4, B = (S + 2) % 4, C = (S + 3) % 4;  // iterations k-3, k-2, k-1
+        // 1. issue the loads of input row yin into slot S (it held row yin - 4)
+        const int32_t yin = y0 - 2 + k;
+        const int32_t rin = region_coord(yin, g.ny, g.periodic[1]);
+        const uint32_t row_in = (uint32_t)(rin >= 0 ? rin : min(max(yin, 0), last));
+        const uint32_t node = ucol + g.nx * row_in;
+        const uint32_t bf = pop_at<QF>(node, 0), bg = pop_at<QG>(node, 0);
+        static_for<0, QF>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            fin[S][i] = St::EF::dec(*elem<O32>(a.fsrc, bf + i * kTile));
+        });
+        static_for<0, QG>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            gin[S][i] = St::EG::dec(*elem<O32>(a.gsrc, bg + i * kTile));
+        });
+        // 2. step t+2 on row y2 = yin - 4 from the step t+1 rows y2 - 1, y2,
+        //    y2 + 1 (computed in iterations k-3, k-2, k-1); stored on the
+        //    strip's own columns for y0 <= y2 < y0 + rows
+        {
+            const int32_t y2 = yin - 4;
+            const bool on = own_col && y2 >= y0 && y2 < y0 + rows;
+            const uint32_t yy = (uint32_t)min(max(y2, 0), last);
+            const uint32_t x = own_col ? (uint32_t)cx : ucol;
+            const Neighbours nb = neighbours(g, x, yy, 0);
+            const RegSrc<St, QF, QG> src{f1[A], f1[B], f1[C], g1[A], g1[B], g1[C]};
+            if constexpr (O32) {
+                const OwnedBufDst<St, QF, QG> dst(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, on);
+                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, BufFlux2{rflux, a.slot2, a.flux_bytes, on});
+            } else {
+                const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, on);
+                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot2, on});
+            }
         }
-        const int32_t gx = region_coord(x0 - 1 + lx, g.nx, g.periodic[0]);
-        const int32_t gy = region_coord(y0 - 1 + ly, g.ny, g.periodic[1]);
-        if (gx < 0 || gy < 0) continue;
-        const uint32_t idx = (uint32_t)gx + g.nx * (uint32_t)gy;
-        const bool own = lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && x0 - 1 + lx < (int32_t)g.nx &&
-                         y0 - 1 + ly < (int32_t)g.ny;
-        const Neighbours nb = neighbours(g, (uint32_t)gx, (uint32_t)gy, 0);
-        const auto src = global_src<St, QF, QG>(g, nb, a.fsrc, a.gsrc, idx);
-        const LdsDst<St> dst{sf, sg, (uint32_t)RN, (uint32_t)(ly * RX + lx)};
-        step_node<2, St>(g, a.c, nb, (uint32_t)gx, (uint32_t)gy, 0u, src, dst, a.flux1, own);
-    }
-    __syncthreads();
-
-    // step t+2 on the tile
-    for (int row = wave; row < TY; row += NW) {
-        const uint32_t x = (uint32_t)(x0 + lane), y = (uint32_t)(y0 + row);
-        if (x >= g.nx || y >= g.ny) continue;
-        const uint32_t idx = x + g.nx * y;
-        const Neighbours nb = neighbours(g, x, y, 0);
-        const LdsSrc<St> src{sf, sg, (uint32_t)RN, (row + 1) * RX + lane + 1, RX};
-        const GlobalDst<St, QF, QG> dst(a.fdst, a.gdst, idx);
-        step_node<2, St>(g, a.c, nb, x, y, 0u, src, dst, a.flux2, true);
+        // 3. step t+1 on row y1 = yin - 2 from the input rows y1 - 1, y1,
+        //    y1 + 1 (loaded in iterations k-3, k-2, k-1), into slot S
+        {
+            const int32_t y1 = yin - 2;
+            const int32_t r1 = region_coord(y1, g.ny, g.periodic[1]);
+            const uint32_t yy = (uint32_t)(r1 >= 0 ? r1 : min(max(y1, 0), last));
+            const Neighbours nb = neighbours(g, ucol, yy, 0);
+            const RegSrc<St, QF, QG> src{fin[A], fin[B], fin[C], gin[A], gin[B], gin[C]};
+            const RegDst<St, QF, QG> dst{f1[S], g1[S]};
+            const bool own = own_col && y1 >= y0 && y1 < y0 + rows;
+            if constexpr (O32) step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, BufFlux2{rflux, a.slot1, a.flux_bytes, own});
+            else step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot1, own});
+        }
+    };
+    // iterations k = 0 .. rows + 5 carry the segment; the count is rounded
+    // up to whole groups of four (the extra ones store nothing)
+    for (int32_t k = 0; k < rows + 6; k += 4) {
+        iteration(std::integral_constant<int, 0>{}, k);
+        iteration(std::integral_constant<int, 1>{}, k + 1);
+        iteration(std::integral_constant<int, 2>{}, k + 2);
+        iteration(std::integral_constant<int, 3>{}, k + 3);
     }
 }
 

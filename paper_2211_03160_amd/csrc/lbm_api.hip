@@ -242,16 +242,11 @@ template <class R> Coef<R> make_coef(const lbm_ctx* c) {
         default: return 0.0;
         }
     };
-    const int qf = qf_of(c->p.dim), qg = qg_of(c->p.dim);
-    for (int r = 0; r < qf; ++r) {
-        const int kind = c->p.dim == 2 ? Flow<2>::kind[r] : Flow<3>::kind[r];
+    for (int kind = 0; kind < 10; ++kind) {
         const double s = flow_rate(kind);
-        k.s[r] = (R)s;
-        k.b[r] = (R)(1.0 - 0.5 * s);
-    }
-    for (int r = 0; r < qg; ++r) {
-        const int kind = c->p.dim == 2 ? Heat<2>::kind[r] : Heat<3>::kind[r];
-        k.q[r] = (R)heat_rate(kind);
+        k.s[kind] = (R)s;
+        k.b[kind] = (R)(1.0 - 0.5 * s);
+        k.q[kind] = (R)heat_rate(kind);
     }
     k.a_t = (R)v[LBM_D_A_T];
     k.gbeta = (R)v[LBM_D_GBETA];
@@ -408,36 +403,48 @@ lbm_status face_sums(lbm_ctx* c, double* host12) {
 
 namespace {
 
-// Tile height of the two-step kernel: the region of (kTile + 2) x (TY + 2)
-// nodes of populations in LDS stays under ~77 KB, so two blocks share a CU.
-template <class St> constexpr int step2_rows() {
-    constexpr int bytes = Flow<2>::Q * (int)sizeof(typename St::TF) + Heat<2>::Q * (int)sizeof(typename St::TG);
-    constexpr int ry = 79000 / ((kTile + 2) * bytes);
-    return ry - 2 < 30 ? ry - 2 : 30;
+// every population array is under 4 GiB: 32-bit byte offsets suffice
+bool fits_o32(const lbm_ctx* c) {
+    const size_t Np = ((size_t)c->geo.N + kTile - 1) / kTile * kTile;
+    const size_t lim = ((size_t)1 << 32) - 65536;  // room for the dropped-lane offsets
+    return Np * qf_of(c->p.dim) * elem_f(c->p.storage) < lim && Np * qg_of(c->p.dim) * elem_g(c->p.storage) < lim;
 }
-constexpr int kStep2Waves = 4;
 
-// k launches of two steps each, A -> B, advancing t by 2k
-template <class St> void step2_launches(lbm_ctx* c, int64_t k) {
-    constexpr int TY = step2_rows<St>();
-    Step2Args<St> a{};
+#ifndef LBM_STREAM_ROWS
+#define LBM_STREAM_ROWS 128
+#endif
+#ifndef LBM_STREAM_WAVES
+#define LBM_STREAM_WAVES 4
+#endif
+
+// k launches of the register-row two-step kernel, A -> B, advancing t by 2k
+template <class St> void stream2_launches(lbm_ctx* c, int64_t k) {
+    constexpr int NWB = LBM_STREAM_WAVES;
+    Stream2Args<St> a{};
     a.geo = c->geo;
     a.c = make_coef<typename St::R>(c);
-    a.tiles_x = (c->geo.nx + kTile - 1) / kTile;
-    a.tiles = a.tiles_x * ((c->geo.ny + TY - 1) / TY);
-    a.tiles_per_xcd = (a.tiles + kXcd - 1) / kXcd;
-    const dim3 grid(a.tiles_per_xcd * kXcd), block(64 * kStep2Waves);
+    a.strips = (c->geo.nx + kStripCols - 1) / kStripCols;
+    a.seg_rows = LBM_STREAM_ROWS;
+    a.units = a.strips * ((c->geo.ny + a.seg_rows - 1) / a.seg_rows);
+    const uint32_t blocks = (a.units + NWB - 1) / NWB;
+    a.blocks_per_xcd = (blocks + kXcd - 1) / kXcd;
+    const dim3 grid(a.blocks_per_xcd * kXcd), block(64 * NWB);
+    const bool o32 = fits_o32(c);
+    const size_t Np = ((size_t)c->geo.N + kTile - 1) / kTile * kTile;
+    a.f_bytes = o32 ? (uint32_t)(Np * Flow<2>::Q * sizeof(typename St::TF)) : 0u;
+    a.g_bytes = o32 ? (uint32_t)(Np * Heat<2>::Q * sizeof(typename St::TG)) : 0u;
+    a.flux = c->flux(0, 0);
+    a.flux_bytes = (uint32_t)(2 * c->lay.flux_doubles * sizeof(double));
     for (int64_t s = 0; s < k; ++s) {
         const auto A = pops<St>(c, c->cur), B = pops<St>(c, 1 - c->cur);
         a.fsrc = A.f;
         a.gsrc = A.g;
         a.fdst = B.f;
         a.gdst = B.g;
-        for (int f = 0; f < 6; ++f) {
-            a.flux1[f] = c->flux((int)((c->t + 1) & 1), f);
-            a.flux2[f] = c->flux((int)((c->t + 2) & 1), f);
-        }
-        hipLaunchKernelGGL((step2_kernel<St, TY, kStep2Waves>), grid, block, 0, c->stream, a);
+        a.slot1 = (uint32_t)(((c->t + 1) & 1) * c->lay.flux_doubles);
+        a.slot2 = (uint32_t)(((c->t + 2) & 1) * c->lay.flux_doubles);
+        if (o32) hipLaunchKernelGGL((stream2_kernel<St, NWB, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((stream2_kernel<St, NWB, false>), grid, block, 0, c->stream, a);
         c->cur = 1 - c->cur;
         c->t += 2;
     }
@@ -617,7 +624,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         using St = decltype(stc);
         if constexpr (DIM == 2) {
             if (c->steps_per_launch == 2 && n >= 2) {
-                step2_launches<St>(c, n / 2);
+                stream2_launches<St>(c, n / 2);
                 n -= n / 2 * 2;
             }
         }

@@ -1,11 +1,12 @@
 """Two steps per launch (2D temporal blocking) against one step per launch.
 
 The two-step kernel applies the same per-node update to the same stored
-values (the intermediate state goes through LDS in the storage type), so the
-whole exported state -- populations, both wall-flux slots and t -- must be
-bitwise identical, in every storage mode and boundary layout, including
-grids smaller than one tile, ragged tiles and an odd step count (which ends
-with a single-step launch).  Parity of the default (two-step) path with the
+values (the intermediate rows stay in registers, rounded through the storage
+type), so the whole exported state -- populations, both wall-flux slots and
+t -- must be bitwise identical, in every storage mode and boundary layout,
+including grids narrower than one strip, grids whose rows wrap more than
+once, ragged strips and segments, and an odd step count (which ends with a
+single-step launch).  Parity of the default (two-step) path with the
 oracle is covered by test_gpu_parity."""
 import numpy as np
 import pytest
@@ -78,3 +79,25 @@ def test_steps_per_launch_arguments():
         c3.steps_per_launch = 2
     assert e.value.status == -5
     c3.steps_per_launch = 1
+
+
+def test_two_step_beyond_4gib_arrays():
+    """FP64 8193^2: each population array exceeds 4 GiB, which takes the
+    two-step kernel's 64-bit addressing path (plain stores under a branch
+    instead of buffer stores).  Moments and wall fluxes must agree bitwise."""
+    import torch
+    cfg = W.rayleigh_benard(2, (8193, 8193), ra=1e8, pr=0.71, storage="fp64")
+    res = []
+    for spl in (1, 2):
+        c = _run(cfg, spl, 3, amp=1e-3)
+        n = c.N
+        rho = torch.empty(n, dtype=torch.float64, device="cuda")
+        u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        T = torch.empty(n, dtype=torch.float64, device="cuda")
+        c._check(lbm.lib().lbm_fields(c._h, rho.data_ptr(), u.data_ptr(), T.data_ptr()))
+        res.append((rho, u, T, c.wall_flux()))
+        del c
+        torch.cuda.empty_cache()
+    (r1, u1, t1, w1), (r2, u2, t2, w2) = res
+    assert torch.equal(r1, r2) and torch.equal(u1, u2) and torch.equal(t1, t2)
+    assert all(np.array_equal(a, b) for a, b in zip(w1, w2))
