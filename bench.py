@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "GLUPS & %HBM peak, FP32 vs FP16-store, 8193² D2Q9+D2Q5 / 385³ D3Q19+D3Q7"
 KERNEL_SOURCES = ["paper_2211_03160_amd/csrc/kernels.hpp", "paper_2211_03160_amd/csrc/lattice.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_d2q9_fp32_8193_counters.txt")
+TRAFFIC_FILES = {2: os.path.join(ROOT, "profiles", "stream2_d2q9_fp32_8193_counters.txt"),
+                 1: os.path.join(ROOT, "profiles", "step_d2q9_fp32_8193_counters.txt")}
 
 
 def log(*a):
@@ -41,13 +42,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per step launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(steps_per_launch):
+    """HBM bytes per launch of the step kernel (two steps or one) from the
+    committed rocprofv3 counter runs, if they were taken on the current
+    kernel source."""
+    path = TRAFFIC_FILES[steps_per_launch]
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -243,7 +246,7 @@ def main():
     bpu = head["bytes_per_update"]
     launch_s = head["ms_per_step"] * spl * 1e-3
     achieved = N * bpu * spl / launch_s / 1e9
-    traffic = read_traffic()
+    traffic = read_traffic(spl)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic,

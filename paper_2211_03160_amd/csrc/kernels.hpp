@@ -268,6 +268,33 @@ template <class St, int QF, int QG, bool O32 = false, bool NT = true> struct Glo
 };
 
 
+// i heads a pair of opposite velocities (i < opp i)
+template <class L> constexpr bool pair_head(int i) { return i != 0 && i < L::opp[i]; }
+
+// +1: row k is even under e -> -e (M_k,opp i = M_k,i); -1: odd
+// (M_k,opp i = -M_k,i, M_k,0 = 0).  Every row of these bases is one or the
+// other.
+template <class L> constexpr int row_parity(int k) {
+    bool even = true, odd = L::M(k, 0) == 0;
+    for (int i = 1; i < L::Q; ++i) {
+        if (L::M(k, i) != L::M(k, L::opp[i])) even = false;
+        if (L::M(k, i) != -L::M(k, L::opp[i])) odd = false;
+    }
+    return even ? 1 : odd ? -1 : 0;
+}
+template <class L> constexpr bool rows_have_parity() {
+    for (int k = 0; k < L::Q; ++k)
+        if (row_parity<L>(k) == 0) return false;
+    return true;
+}
+static_assert(rows_have_parity<Flow<2>>() && rows_have_parity<Flow<3>>() && rows_have_parity<Heat<2>>() &&
+                  rows_have_parity<Heat<3>>(),
+              "every moment row must be even or odd");
+
+// 1/x: the hardware reciprocal in FP32 (1 ulp), exact division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Returns false if the node's density or temperature is not finite.
 template <int DIM, class St, class Dst>
 __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R* hg,
@@ -277,20 +304,65 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
     using H = Heat<DIM>;
     constexpr int QF = L::Q, QG = H::Q;
 
-    R drho = R(0), j[3] = {R(0), R(0), R(0)}, dT = R(0);
-    static_for<0, QF>([&](auto ic) {
+    // Opposite velocities pair up (i, opp i); every moment row is even
+    // (M_k,opp i = M_k,i) or odd (M_k,opp i = -M_k,i, M_k,0 = 0), so even
+    // rows are sums over the pair sums S and odd rows over the pair
+    // differences D, and the inverse transform gives each pair an even part
+    // e and an odd part o: h_i += e + o, h_opp i += e - o.
+    R S[QF], D[QF];  // at pair heads
+    static_for<1, QF>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        drho += hf[i];
-        cmac<L::ex[i]>(j[0], hf[i]);
-        cmac<L::ey[i]>(j[1], hf[i]);
-        cmac<L::ez[i]>(j[2], hf[i]);
+        if constexpr (pair_head<L>(i)) {
+            S[i] = hf[i] + hf[L::opp[i]];
+            D[i] = hf[i] - hf[L::opp[i]];
+        }
     });
-    static_for<0, QG>([&](auto ic) { dT += hg[decltype(ic)::value]; });
+    auto flow_moment = [&](auto kc) -> R {
+        constexpr int k = decltype(kc)::value;
+        constexpr int par = row_parity<L>(k);
+        R mk = R(0);
+        if constexpr (par > 0) cmac<L::M(k, 0)>(mk, hf[0]);
+        static_for<1, QF>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (pair_head<L>(i)) cmac<L::M(k, i)>(mk, par > 0 ? S[i] : D[i]);
+        });
+        return mk;
+    };
+    const R drho = flow_moment(std::integral_constant<int, 0>{});
+    R j[3] = {R(0), R(0), R(0)};
+    static_for<1, QF>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (pair_head<L>(i)) {
+            cmac<L::ex[i]>(j[0], D[i]);
+            cmac<L::ey[i]>(j[1], D[i]);
+            cmac<L::ez[i]>(j[2], D[i]);
+        }
+    });
+    R Sg[QG], Dg[QG];
+    static_for<1, QG>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (pair_head<H>(i)) {
+            Sg[i] = hg[i] + hg[H::opp[i]];
+            Dg[i] = hg[i] - hg[H::opp[i]];
+        }
+    });
+    auto heat_moment = [&](auto kc) -> R {
+        constexpr int k = decltype(kc)::value;
+        constexpr int par = row_parity<H>(k);
+        R nk = R(0);
+        if constexpr (par > 0) cmac<H::M(k, 0)>(nk, hg[0]);
+        static_for<1, QG>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if constexpr (pair_head<H>(i)) cmac<H::M(k, i)>(nk, par > 0 ? Sg[i] : Dg[i]);
+        });
+        return nk;
+    };
+    const R dT = heat_moment(std::integral_constant<int, 0>{});
     const R rho = R(1) + drho;
     const R T = c.t_base + dT;
     R F[3] = {R(0), R(0), R(0)};
     F[DIM - 1] = rho * c.gbeta * (dT + c.tb_m_t0);  // buoyancy, upward
-    const R inv_rho = R(1) / rho;
+    const R inv_rho = recip(rho);
     R u[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + R(0.5) * F[a]) * inv_rho;
@@ -306,23 +378,31 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
         } else if constexpr (kind == kJx || kind == kJy || kind == kJz) {
             d = F[kind - kJx];  // momentum gains exactly F for any rate
         } else {
-            R mk = R(0);
-            static_for<0, QF>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                cmac<L::M(k, i)>(mk, hf[i]);
-            });
+            const R mk = flow_moment(kc);
             d = -c.s[kind] * (mk - eq_dev<DIM>(k, rho, drho, u)) + c.b[kind] * force_mom<DIM>(k, u, F);
         }
         dm[k] = d * R(1.0 / row_norm<L>(k));
     });
-    static_for<0, QF>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        R acc = hf[i];
+    {
+        R acc = hf[0];
         static_for<1, QF>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            cmac<L::M(k, i)>(acc, dm[k]);
+            if constexpr (row_parity<L>(k) > 0) cmac<L::M(k, 0)>(acc, dm[k]);
         });
-        hf[i] = acc;
+        hf[0] = acc;
+    }
+    static_for<1, QF>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (pair_head<L>(i)) {
+            R e = R(0), o = R(0);
+            static_for<1, QF>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if constexpr (row_parity<L>(k) > 0) cmac<L::M(k, i)>(e, dm[k]);
+                else cmac<L::M(k, i)>(o, dm[k]);
+            });
+            hf[L::opp[i]] += e - o;
+            hf[i] += e + o;
+        }
     });
 
     // thermal: n_eq = (T, u T, a_T T, 0...) in deviation form
@@ -330,26 +410,37 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
     static_for<0, QG>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr int kind = H::kind[k];
-        R nk = R(0);
-        static_for<0, QG>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            cmac<H::M(k, i)>(nk, hg[i]);
-        });
         R d;
-        if constexpr (kind == kRho) d = R(0);
-        else if constexpr (kind == kJx || kind == kJy || kind == kJz) d = -c.q[kind] * (nk - u[kind - kJx] * T);
-        else if constexpr (kind == kE) d = -c.q[kind] * (nk - c.a_t * dT);
-        else d = -c.q[kind] * nk;
+        if constexpr (kind == kRho) {
+            d = R(0);
+        } else {
+            const R nk = heat_moment(kc);
+            if constexpr (kind == kJx || kind == kJy || kind == kJz) d = -c.q[kind] * (nk - u[kind - kJx] * T);
+            else if constexpr (kind == kE) d = -c.q[kind] * (nk - c.a_t * dT);
+            else d = -c.q[kind] * nk;
+        }
         dn[k] = d * R(1.0 / row_norm<H>(k));
     });
-    static_for<0, QG>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        R acc = hg[i];
+    {
+        R acc = hg[0];
         static_for<1, QG>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            cmac<H::M(k, i)>(acc, dn[k]);
+            if constexpr (row_parity<H>(k) > 0) cmac<H::M(k, 0)>(acc, dn[k]);
         });
-        hg[i] = acc;
+        hg[0] = acc;
+    }
+    static_for<1, QG>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (pair_head<H>(i)) {
+            R e = R(0), o = R(0);
+            static_for<1, QG>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if constexpr (row_parity<H>(k) > 0) cmac<H::M(k, i)>(e, dn[k]);
+                else cmac<H::M(k, i)>(o, dn[k]);
+            });
+            hg[H::opp[i]] += e - o;
+            hg[i] += e + o;
+        }
     });
 
     // store post-collision populations at the node
@@ -403,18 +494,6 @@ struct PtrFlux {  // per-face arrays
     }
 };
 
-// the faces of one slot back to back (face f starts after the node counts
-// of faces 0 .. f-1) in a buffer; writes with dropped lanes, no branch (2D)
-struct BufFlux2 {
-    __amdgpu_buffer_rsrc_t r;
-    uint32_t slot;  // first element of the slot
-    uint32_t drop;  // byte offset beyond the buffer
-    bool on;
-    template <int face> __device__ void put(const Geometry& g, uint32_t local, double v, bool wall) const {
-        const uint32_t start = face == 0 ? 0u : face == 1 ? g.ny : face == 2 ? 2u * g.ny : 2u * g.ny + g.nx;
-        buffer_store(v, r, on && wall ? (slot + start + local) * 8u : drop);
-    }
-};
 
 // ----------------------------------------------------------------- the step
 // Sources of the pull.  pull_f<i, ex, ey, ez, o>(out) returns the decoded
@@ -579,6 +658,10 @@ __device__ __forceinline__ int32_t region_coord(int32_t v, uint32_t n, int32_t p
 // row's loads are issued one whole iteration before their first use, so
 // every wavefront keeps a row of loads in flight while it computes.
 constexpr int kStripCols = 60;
+#ifndef LBM_STREAM_AHEAD
+#define LBM_STREAM_AHEAD 1
+#endif
+constexpr int kStreamAhead = LBM_STREAM_AHEAD;  // rows between a row's loads and their first use
 
 // the value of v held by lane l - 1 (FromLeft) or lane l + 1 (otherwise)
 template <bool FromLeft> __device__ __forceinline__ float lane_shift(float v) {
@@ -659,7 +742,11 @@ template <class St, int QF, int QG> struct OwnedGlobalDst : GlobalDst<St, QF, QG
     }
 };
 
-// flux slot in one array, faces back to back (2D), plain stores under a branch
+// One flux slot in one array, the faces back to back (face f starts after
+// the node counts of faces 0 .. f-1; 2D).  Plain stores under a branch: only
+// lanes on a wall store, so the branch is almost never taken, and then the
+// compiler's assumption that the stores were not issued is exact (dropped-
+// lane buffer stores would cost a vector-memory issue slot each, every row).
 struct PtrFlux2 {
     double* base;
     uint32_t slot;
@@ -677,7 +764,6 @@ template <class St> struct Stream2Args {
     typename St::TG* gdst;
     double* flux;                     // wall heat flux area: two slots, faces back to back
     uint32_t f_bytes, g_bytes;        // sizes of fdst, gdst (buffer stores)
-    uint32_t flux_bytes;              // size of the flux area
     uint32_t slot1, slot2;            // first element of the slots of steps t+1, t+2
     Geometry geo;
     Coef<typename St::R> c;
@@ -687,9 +773,15 @@ template <class St> struct Stream2Args {
     uint32_t blocks_per_xcd;
 };
 
-// Register budget: four wavefronts per SIMD (128 registers) with FP32
-// arithmetic, two with FP64, whose rows take twice the registers.
-template <class St> constexpr int stream_waves_per_simd() { return sizeof(typename St::R) == 8 ? 2 : 4; }
+// Register budget: three wavefronts per SIMD (168 registers) with FP32
+// arithmetic, two with FP64, whose rows take twice the registers.  (At
+// four, 128 registers, the FP32 kernel spills and runs slower.)
+#ifndef LBM_STREAM_WAVES_PER_SIMD
+#define LBM_STREAM_WAVES_PER_SIMD 3
+#endif
+template <class St> constexpr int stream_waves_per_simd() {
+    return sizeof(typename St::R) == 8 ? 2 : LBM_STREAM_WAVES_PER_SIMD;
+}
 
 template <class St, int NWB, bool O32>
 __global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St>())))
@@ -709,10 +801,14 @@ void stream2_kernel(Stream2Args<St> a) {
     const uint32_t ucol = col < 0 ? 0u : (uint32_t)col;     // any in-domain column for dead lanes
     const bool own_col = lane >= 2 && lane < 2 + kStripCols && cx < (int32_t)g.nx;
 
+    // Rings: NI input rows (a row is loaded D iterations before its first
+    // use), NS step t+1 rows; the loop is unrolled over U iterations so that
+    // every ring index is a compile-time constant.
+    constexpr int D = kStreamAhead, NI = D + 3, NS = NI % 3 == 0 ? 3 : NI, U = NI;
     // rows a step never fills (beyond a wall) are only ever discarded by the
     // bounce-back selects; start them at zero so no value is indeterminate
-    R fin[4][QF] = {}, gin[4][QG] = {};  // input rows, ring of four
-    R f1[4][QF] = {}, g1[4][QG] = {};    // step t+1 rows, ring of four
+    R fin[NI][QF] = {}, gin[NI][QG] = {};  // input rows
+    R f1[NS][QF] = {}, g1[NS][QG] = {};    // step t+1 rows
 
     // The loop body is straight-line: every iteration loads a row and
     // computes both steps; rows outside the segment or beyond a wall use an
@@ -721,11 +817,12 @@ void stream2_kernel(Stream2Args<St> a) {
     // the compiler drains every outstanding load before the next row.)
     const int32_t last = (int32_t)g.ny - 1;
     const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
-    const __amdgpu_buffer_rsrc_t rflux = buffer_rsrc(a.flux, a.flux_bytes);
     auto iteration = [&](auto slot, int32_t k) {
-        constexpr int S = decltype(slot)::value;  // k mod 4
-        constexpr int A = (S + 1) % 4, B = (S + 2) % 4, C = (S + 3) % 4;  // iterations k-3, k-2, k-1
-        // 1. issue the loads of input row yin into slot S (it held row yin - 4)
+        constexpr int S = decltype(slot)::value;  // k mod U
+        // ring slot of what iteration k - j loaded (input) or computed (step t+1)
+        constexpr auto in = [](int j) { return ((S - j) % NI + NI) % NI; };
+        constexpr auto s1 = [](int j) { return ((S - j) % NS + NS) % NS; };
+        // 1. issue the loads of input row yin (its slot held row yin - NI)
         const int32_t yin = y0 - 2 + k;
         const int32_t rin = region_coord(yin, g.ny, g.periodic[1]);
         const uint32_t row_in = (uint32_t)(rin >= 0 ? rin : min(max(yin, 0), last));
@@ -733,51 +830,49 @@ void stream2_kernel(Stream2Args<St> a) {
         const uint32_t bf = pop_at<QF>(node, 0), bg = pop_at<QG>(node, 0);
         static_for<0, QF>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            fin[S][i] = St::EF::dec(*elem<O32>(a.fsrc, bf + i * kTile));
+            fin[in(0)][i] = St::EF::dec(*elem<O32>(a.fsrc, bf + i * kTile));
         });
         static_for<0, QG>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            gin[S][i] = St::EG::dec(*elem<O32>(a.gsrc, bg + i * kTile));
+            gin[in(0)][i] = St::EG::dec(*elem<O32>(a.gsrc, bg + i * kTile));
         });
-        // 2. step t+2 on row y2 = yin - 4 from the step t+1 rows y2 - 1, y2,
+        // 2. step t+2 on row y2 = y1 - 2 from the step t+1 rows y2 - 1, y2,
         //    y2 + 1 (computed in iterations k-3, k-2, k-1); stored on the
         //    strip's own columns for y0 <= y2 < y0 + rows
         {
-            const int32_t y2 = yin - 4;
+            const int32_t y2 = yin - 3 - D;
             const bool on = own_col && y2 >= y0 && y2 < y0 + rows;
             const uint32_t yy = (uint32_t)min(max(y2, 0), last);
             const uint32_t x = own_col ? (uint32_t)cx : ucol;
             const Neighbours nb = neighbours(g, x, yy, 0);
-            const RegSrc<St, QF, QG> src{f1[A], f1[B], f1[C], g1[A], g1[B], g1[C]};
+            const RegSrc<St, QF, QG> src{f1[s1(3)], f1[s1(2)], f1[s1(1)], g1[s1(3)], g1[s1(2)], g1[s1(1)]};
             if constexpr (O32) {
                 const OwnedBufDst<St, QF, QG> dst(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, on);
-                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, BufFlux2{rflux, a.slot2, a.flux_bytes, on});
+                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot2, on});
             } else {
                 const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, on);
                 step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot2, on});
             }
         }
-        // 3. step t+1 on row y1 = yin - 2 from the input rows y1 - 1, y1,
-        //    y1 + 1 (loaded in iterations k-3, k-2, k-1), into slot S
+        // 3. step t+1 on row y1 = yin - 1 - D from the input rows y1 - 1, y1,
+        //    y1 + 1 (loaded in iterations k-2-D, k-1-D, k-D), into the slot
+        //    step 2 has just read its row y2 - 1 from
         {
-            const int32_t y1 = yin - 2;
+            const int32_t y1 = yin - 1 - D;
             const int32_t r1 = region_coord(y1, g.ny, g.periodic[1]);
             const uint32_t yy = (uint32_t)(r1 >= 0 ? r1 : min(max(y1, 0), last));
             const Neighbours nb = neighbours(g, ucol, yy, 0);
-            const RegSrc<St, QF, QG> src{fin[A], fin[B], fin[C], gin[A], gin[B], gin[C]};
-            const RegDst<St, QF, QG> dst{f1[S], g1[S]};
+            const RegSrc<St, QF, QG> src{fin[in(2 + D)], fin[in(1 + D)], fin[in(D)],
+                                         gin[in(2 + D)], gin[in(1 + D)], gin[in(D)]};
+            const RegDst<St, QF, QG> dst{f1[s1(0)], g1[s1(0)]};
             const bool own = own_col && y1 >= y0 && y1 < y0 + rows;
-            if constexpr (O32) step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, BufFlux2{rflux, a.slot1, a.flux_bytes, own});
-            else step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot1, own});
+            step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot1, own});
         }
     };
-    // iterations k = 0 .. rows + 5 carry the segment; the count is rounded
-    // up to whole groups of four (the extra ones store nothing)
-    for (int32_t k = 0; k < rows + 6; k += 4) {
-        iteration(std::integral_constant<int, 0>{}, k);
-        iteration(std::integral_constant<int, 1>{}, k + 1);
-        iteration(std::integral_constant<int, 2>{}, k + 2);
-        iteration(std::integral_constant<int, 3>{}, k + 3);
+    // iterations k = 0 .. rows + 4 + D carry the segment; the count is
+    // rounded up to whole groups of U (the extra ones store nothing)
+    for (int32_t k = 0; k < rows + 5 + D; k += U) {
+        static_for<0, U>([&](auto sc) { iteration(sc, k + decltype(sc)::value); });
     }
 }
 

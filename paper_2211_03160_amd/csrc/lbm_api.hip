@@ -434,7 +434,6 @@ template <class St> void stream2_launches(lbm_ctx* c, int64_t k) {
     a.f_bytes = o32 ? (uint32_t)(Np * Flow<2>::Q * sizeof(typename St::TF)) : 0u;
     a.g_bytes = o32 ? (uint32_t)(Np * Heat<2>::Q * sizeof(typename St::TG)) : 0u;
     a.flux = c->flux(0, 0);
-    a.flux_bytes = (uint32_t)(2 * c->lay.flux_doubles * sizeof(double));
     for (int64_t s = 0; s < k; ++s) {
         const auto A = pops<St>(c, c->cur), B = pops<St>(c, 1 - c->cur);
         a.fsrc = A.f;
