@@ -11,7 +11,7 @@ against an FP64 GPU run of the same steps, the 16-bit storage forms and the
 bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
-       [--only NAME] [--no-cpu] [--copy-probe]
+       [--only NAME] [--no-cpu] [--copy-probe] [--oracle-timing]
 """
 import argparse
 import hashlib
@@ -175,6 +175,56 @@ def cpu_baseline(cfg2d, budget_s=12.0):
                       f"(same rows, walls and lattice parameters), {steps} steps in {dt:.1f} s"}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_timing():
+    """The FP64 oracle timed in full: C0 (129^2, all 5000 steps), the C1 and
+    C2 shapes (3 steps after 1 warm-up), each on all host threads and, for
+    C0 and a C1 strip, on one thread.  Host memory: ~15 GB (C1) and ~24 GB
+    (C2) of FP64 populations."""
+    from oracle.lbmref import Oracle, set_threads, threads
+    from paper_2211_03160_amd import workloads as W
+    all_threads = threads()
+    out = {"cpu": cpu_model(), "threads": all_threads, "cases": []}
+
+    def timed(name, cfg, warm, steps, nthreads):
+        set_threads(nthreads)
+        o = Oracle(cfg)
+        o.init(W.SEED, W.NOISE)
+        if warm:
+            o.step(warm)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+        n = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+        r = {"case": name, "nodes": n, "steps": steps, "threads": nthreads, "seconds": round(dt, 3),
+             "mlups": round(n * steps / dt / 1e6, 3)}
+        log("oracle", json.dumps(r))
+        out["cases"].append(r)
+        del o
+
+    c0 = W.C0["cfg"]
+    timed("C0 129^2 D2Q9+D2Q5, 5000 steps", c0, 0, W.C0["steps"], all_threads)
+    timed("C0 129^2, 200 steps", c0, 0, 200, 1)
+    strip = dict(W.C1["cfg"])
+    strip["n"] = (8193, 65, 1)
+    d = __import__("paper_2211_03160_amd.lbm", fromlist=["derive"]).derive(W.C1["cfg"])
+    strip.update(nu=d["nu"], alpha=d["alpha"], gbeta=d["gbeta"], storage="fp64")
+    timed("C1 strip 8193x65, 3 steps", strip, 1, 3, 1)
+    timed("C1 8193^2 D2Q9+D2Q5, 3 steps", W.with_storage(W.C1["cfg"], "fp64"), 1, 3, all_threads)
+    timed("C2 385^3 D3Q19+D3Q7, 3 steps", W.with_storage(W.C2["cfg"], "fp64"), 1, 3, all_threads)
+    set_threads(0)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +235,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (for counter calibration)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the FP64 oracle on C0 in full and the C1/C2 shapes, then exit")
     args = ap.parse_args()
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the fused step has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
