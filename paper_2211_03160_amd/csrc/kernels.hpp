@@ -24,6 +24,13 @@
 // rounds away any deviation below half an ulp of w (~1.5e-8) every step.
 // With orthogonal bases the collision is applied as an increment:
 //   h+_i = h_i + sum_k M_ki dm_k / |M_k|^2.
+//
+// In 2D, stream2_kernel advances two steps per launch: each wavefront walks
+// down a strip of columns keeping the last rows of the input and of the
+// intermediate step in registers, so the intermediate state never goes to
+// memory; every node update is the same step_node arithmetic on the same
+// (storage-rounded) values, so the result is bitwise that of two single
+// steps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -482,10 +489,6 @@ __device__ __forceinline__ void buffer_store(T v, __amdgpu_buffer_rsrc_t r, uint
 // Wall heat flux sinks: put<face>(g, local, value, wall) records the value
 // of a link that crosses a Dirichlet wall (wall true) at index `local` of
 // that face.
-struct NoFlux {
-    template <int face> __device__ void put(const Geometry&, uint32_t, double, bool) const {}
-};
-
 struct PtrFlux {  // per-face arrays
     double* const* flux;
     bool on;
