@@ -2,13 +2,16 @@
 
 Headline: GLUPS of the FP32 fused step on the 8193 x 8193 D2Q9 + D2Q5
 Rayleigh-Benard cell (Ra 1e8, Pr 0.71), W untimed warm-up steps then K timed
-steps, inputs resident in HBM.  GLUPS = nodes x steps / time / 1e9 (the
+steps, inputs resident in HBM, in the library's default launch mode (four
+steps per launch for FP32 in 2D).  GLUPS = nodes x steps / time / 1e9 (the
 MLUPS definition of Section 2.3, Eq. 10, in units of 1e9).  The same JSON
-line carries the roofline of the step kernel (algorithmic bytes per launch /
-measured launch time against the 8 TB/s HBM peak), the Nu error of the run
-against an FP64 GPU run of the same steps, the 16-bit storage forms and the
-385^3 D3Q19 + D3Q7 cell beside it, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+line carries the roofline of the dominant kernel (with several steps per
+launch it is bound by vector ALU issue: algorithmic FP32 flops per second
+against the non-packed FP32 peak, with the HBM fraction beside it; with one
+step per launch, algorithmic bytes per launch against the 8 TB/s HBM peak),
+the Nu error of the run against an FP64 GPU run of the same steps, the
+other launch modes and storage forms, the 385^3 D3Q19 + D3Q7 cell, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
        [--only NAME] [--no-cpu] [--copy-probe] [--oracle-timing]
@@ -27,8 +30,17 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "GLUPS & %HBM peak, FP32 vs FP16-store, 8193² D2Q9+D2Q5 / 385³ D3Q19+D3Q7"
 KERNEL_SOURCES = ["paper_2211_03160_amd/csrc/kernels.hpp", "paper_2211_03160_amd/csrc/lattice.hpp"]
-TRAFFIC_FILES = {2: os.path.join(ROOT, "profiles", "stream2_d2q9_fp32_8193_counters.txt"),
+TRAFFIC_FILES = {4: os.path.join(ROOT, "profiles", "stream4_d2q9_fp32_8193_counters.txt"),
                  1: os.path.join(ROOT, "profiles", "step_d2q9_fp32_8193_counters.txt")}
+# FP32 operations per 2D lattice update in the kernels' formulation (adds,
+# subtracts, multiplies and the reciprocal 1 each, fused multiply-adds 2),
+# counted in the one-step kernel, which computes every node once
+FLOPS_PER_UPDATE_2D = 209
+# non-packed FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
+# x 2.4 GHz.  The build disables packed FP32, whose dual-rate issue gives the
+# published 157.3; both are reported.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 
 
 def log(*a):
@@ -46,8 +58,8 @@ def read_traffic(steps_per_launch):
     """HBM bytes per launch of the step kernel (two steps or one) from the
     committed rocprofv3 counter runs, if they were taken on the current
     kernel source."""
-    path = TRAFFIC_FILES[steps_per_launch]
-    if not os.path.exists(path):
+    path = TRAFFIC_FILES.get(steps_per_launch)
+    if path is None or not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
@@ -260,6 +272,7 @@ def main():
     cases = {
         "rb2d_8193_fp32": (cfg32, Wm, K),
         "rb2d_8193_fp32_1": (cfg32, Wm, K),
+        "rb2d_8193_fp32_2": (cfg32, Wm, K),
         "rb2d_8193_fp64": (W.with_storage(cfg32, "fp64"), Wm, K),
         "rb2d_8193_fp16": (W.with_storage(cfg32, "fp16"), Wm, K),
         "rb2d_8193_bf16": (W.with_storage(cfg32, "bf16"), Wm, K),
@@ -282,8 +295,9 @@ def main():
     if args.only:
         for name in args.only.split(","):
             cfg, w, k = cases[name]
+            spl = {"_1": 1, "_2": 2}.get(name[-2:])
             r = run_case(cfg, min(w, args.warmup), min(k, args.steps), seed, noise, want_nu=False,
-                         steps_per_launch=1 if name.endswith("_1") else None)
+                         steps_per_launch=spl)
             log(name, json.dumps(r))
         return
 
@@ -293,29 +307,38 @@ def main():
     ref64 = run_case(cases["rb2d_8193_fp64"][0], Wm, K, seed, noise)
     log("fp64", json.dumps(ref64))
 
-    # the dominant kernel: two steps per launch (K and W even, so every
-    # timed launch is one), algorithmic bytes = one read and one write of
-    # all populations per node and launch
+    # The dominant kernel: several steps per launch (K and W are multiples
+    # of the steps per launch, so every timed launch is one).  Its
+    # algorithmic HBM traffic is one read and one write of all populations
+    # per node and launch; with four steps that is 28 B per update, and the
+    # kernel is bound by vector ALU issue, so the roofline is the FP32 one.
     N = cfg32["n"][0] * cfg32["n"][1]
     spl = head["steps_per_launch"]
     bpu = head["bytes_per_update"]
     launch_s = head["ms_per_step"] * spl * 1e-3
-    achieved = N * bpu * spl / launch_s / 1e9
+    hbm_gbs = N * bpu * spl / launch_s / 1e9
     traffic = read_traffic(spl)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": traffic,
-                "kernel": "lbm::stream2_kernel<StF32, 4, true>" if spl == 2 else "lbm::step_kernel<2, StF32>",
-                "steps_per_launch": spl,
-                "launch_ms": round(launch_s * 1e3, 4),
-                "bytes_per_node_per_launch": bpu * spl,
-                "bytes_per_lattice_update": bpu}
+    if spl > 1:
+        tflops = head["glups"] * FLOPS_PER_UPDATE_2D / 1e3
+        roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                    "kernel": f"lbm::stream_kernel<StF32, 4, true, {spl}, 0>",
+                    "flops_per_lattice_update": FLOPS_PER_UPDATE_2D,
+                    "frac_of_packed_fp32_peak": round(tflops / PEAK_FP32_PACKED_TFLOPS, 4),
+                    "hbm_algorithmic_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / PEAK_HBM_GBS, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(hbm_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+                    "kernel": "lbm::step_kernel<2, StF32>"}
+    roofline.update({"steps_per_launch": spl, "launch_ms": round(launch_s * 1e3, 4),
+                     "bytes_per_node_per_launch": bpu * spl, "bytes_per_lattice_update": bpu})
 
     variants = {"rb2d_8193_fp64": {**ref64}}
-    one = run_case(cfg32, Wm, K, seed, noise, want_nu=False, steps_per_launch=1)
-    one["hbm_frac"] = one["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
-    variants["rb2d_8193_fp32_one_step_per_launch"] = one
-    log("fp32 one step per launch", json.dumps(one))
+    for k, name in ((1, "one"), (2, "two")):
+        r = run_case(cfg32, Wm, K, seed, noise, want_nu=False, steps_per_launch=k)
+        r["hbm_frac"] = r["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
+        variants[f"rb2d_8193_fp32_{name}_step{'s' if k > 1 else ''}_per_launch"] = r
+        log(f"fp32 {name} step(s) per launch", json.dumps(r))
     if not args.quick:
         for name in ("rb2d_8193_fp16", "rb2d_8193_bf16", "rb2d_8193_mixed"):
             cfg, w, k = cases[name]

@@ -166,18 +166,21 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
                            const double* T);
 
 /* Enqueues n fused steps (n = 0: no-op; n < 0: LBM_E_INVALID).  In 2D
- * the steps go two per launch by default (see lbm_set_steps_per_launch);
- * an odd n ends with a single-step launch.                              */
+ * several steps go per launch (see lbm_set_steps_per_launch); a count that
+ * does not divide n ends with shorter launches.                         */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
-/* Steps per kernel launch of lbm_step: 1, or 2 (2D only; the default in
- * 2D).  With 2, each wavefront walks down a strip of columns row by row,
- * keeping the last rows of step t and of step t+1 in registers, and
- * writes step t+2: the update of every node is the same arithmetic on the
- * same stored values as with 1, so the results are bitwise identical;
- * only the global memory traffic per step halves.  LBM_E_INVALID for
- * other values, LBM_E_UNSUPPORTED for 2 in 3D, LBM_E_STATE for a batch
- * member.                                                               */
+/* Steps per kernel launch of lbm_step: 1 .. 4 (more than 1 in 2D only).
+ * A 2D context starts with the count measured fastest for its storage:
+ * 4 (FP32), 3 (FP16, FP16-f+FP32-g), 2 (BF16, FP64); 3D contexts with 1.
+ * With k > 1, each wavefront walks down a strip of
+ * columns row by row, keeping the last rows of step t and of the
+ * intermediate steps in registers, and writes step t+k: the update of every
+ * node is the same arithmetic on the same stored values as with 1, so the
+ * results are bitwise identical; only the global memory traffic per step
+ * drops to 1/k.  A count of steps that k does not divide ends with shorter
+ * launches.  LBM_E_INVALID for other values, LBM_E_UNSUPPORTED for k > 1
+ * in 3D, LBM_E_STATE for a batch member.                               */
 lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps);
 int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
 

@@ -25,12 +25,12 @@
 // With orthogonal bases the collision is applied as an increment:
 //   h+_i = h_i + sum_k M_ki dm_k / |M_k|^2.
 //
-// In 2D, stream2_kernel advances two steps per launch: each wavefront walks
-// down a strip of columns keeping the last rows of the input and of the
-// intermediate step in registers, so the intermediate state never goes to
-// memory; every node update is the same step_node arithmetic on the same
-// (storage-rounded) values, so the result is bitwise that of two single
-// steps.
+// In 2D, stream_kernel advances two or three steps per launch: each
+// wavefront walks down a strip of columns keeping the last rows of the
+// input and of the intermediate steps in registers, so the intermediate
+// states never go to memory; every node update is the same step_node
+// arithmetic on the same (storage-rounded) values, so the result is
+// bitwise that of single steps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -649,22 +649,20 @@ __device__ __forceinline__ int32_t region_coord(int32_t v, uint32_t n, int32_t p
     return r < 0 ? r + (int32_t)n : r;
 }
 
-// ------------------------------------- two steps per launch, register rows
-// A wavefront walks down a strip of kStripCols columns, one row per
-// iteration.  Lane l holds column x0 - 2 + l.  The last rows of the input
-// state and of step t+1 stay in registers as decoded values (rounded through
-// the storage type, so exactly what a single step would store and reload);
-// the x-neighbours of a lane come from its neighbour lanes by DPP wave
-// shifts.  Step t+1 is valid on lanes 1..62, step t+2 on lanes 2..61, which
-// are the strip's own columns.  Row iteration k loads input row y0 - 2 + k,
-// computes step t+2 on row y0 - 6 + k and step t+1 on row y0 - 4 + k: a
-// row's loads are issued one whole iteration before their first use, so
-// every wavefront keeps a row of loads in flight while it computes.
-constexpr int kStripCols = 60;
-#ifndef LBM_STREAM_AHEAD
-#define LBM_STREAM_AHEAD 1
-#endif
-constexpr int kStreamAhead = LBM_STREAM_AHEAD;  // rows between a row's loads and their first use
+// ----------------------------- several steps per launch, register rows (2D)
+// A wavefront walks down a strip of 64 - 2 NS columns, one row per
+// iteration, and advances them NS steps (NS = 2 .. 4).  Lane l holds column
+// x0 - NS + l.  The last rows of the input state and of every intermediate
+// step stay in registers as decoded values (rounded through the storage
+// type, so exactly what a single step would store and reload); the
+// x-neighbours of a lane come from its neighbour lanes by DPP wave shifts.
+// Step j is valid on lanes j .. 63 - j, so step NS covers the strip's own
+// columns (lanes NS .. 63 - NS).  Row iteration k loads input row
+// y0 - NS + k; step 1 runs D + 1 rows behind it (the loads of a row are
+// issued D iterations before their first use) and every further step two
+// rows behind the one before, computed in the order NS, ..., 2, 1 so that
+// each step reads the rows of the step before it from earlier iterations.
+template <int NS> constexpr int strip_cols() { return 64 - 2 * NS; }
 
 // the value of v held by lane l - 1 (FromLeft) or lane l + 1 (otherwise)
 template <bool FromLeft> __device__ __forceinline__ float lane_shift(float v) {
@@ -760,14 +758,15 @@ struct PtrFlux2 {
     }
 };
 
-template <class St> struct Stream2Args {
+template <class St> struct StreamArgs {
     const typename St::TF* fsrc;
     const typename St::TG* gsrc;
     typename St::TF* fdst;
     typename St::TG* gdst;
     double* flux;                     // wall heat flux area: two slots, faces back to back
     uint32_t f_bytes, g_bytes;        // sizes of fdst, gdst (buffer stores)
-    uint32_t slot1, slot2;            // first element of the slots of steps t+1, t+2
+    uint32_t slot[2];                 // first element of flux slot 0 and slot 1
+    int32_t t_parity;                 // (t of the input state) mod 2: step j writes slot (t + j) mod 2
     Geometry geo;
     Coef<typename St::R> c;
     uint32_t strips;          // strips across x
@@ -777,44 +776,47 @@ template <class St> struct Stream2Args {
 };
 
 // Register budget: three wavefronts per SIMD (168 registers) with FP32
-// arithmetic, two with FP64, whose rows take twice the registers.  (At
-// four, 128 registers, the FP32 kernel spills and runs slower.)
+// arithmetic and two steps, two with three steps or FP64, whose rows take
+// more registers.  (At four, 128 registers, the two-step FP32 kernel spills
+// and runs slower.)
 #ifndef LBM_STREAM_WAVES_PER_SIMD
 #define LBM_STREAM_WAVES_PER_SIMD 3
 #endif
-template <class St> constexpr int stream_waves_per_simd() {
-    return sizeof(typename St::R) == 8 ? 2 : LBM_STREAM_WAVES_PER_SIMD;
+template <class St, int NS> constexpr int stream_waves_per_simd() {
+    return sizeof(typename St::R) == 8 || NS > 2 ? 2 : LBM_STREAM_WAVES_PER_SIMD;
 }
 
-template <class St, int NWB, bool O32>
-__global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St>())))
-void stream2_kernel(Stream2Args<St> a) {
+template <class St, int NWB, bool O32, int NS, int D>
+__global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St, NS>())))
+void stream_kernel(StreamArgs<St> a) {
     using R = typename St::R;
     constexpr int QF = Flow<2>::Q, QG = Heat<2>::Q;
+    constexpr int W = strip_cols<NS>();
+    static_assert(NS >= 2 && NS <= 4, "two to four steps per launch");
     const Geometry& g = a.geo;
     const int lane = (int)(threadIdx.x & 63);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t unit = logical_block(a.blocks_per_xcd) * NWB + wave;
     if (unit >= a.units) return;  // whole wavefront
-    const int32_t x0 = (int32_t)((unit % a.strips) * kStripCols);
+    const int32_t x0 = (int32_t)((unit % a.strips) * W);
     const int32_t y0 = (int32_t)((unit / a.strips) * a.seg_rows);
     const int32_t rows = min((int32_t)a.seg_rows, (int32_t)g.ny - y0);
-    const int32_t cx = x0 - 2 + lane;                       // this lane's column, unwrapped
+    const int32_t cx = x0 - NS + lane;                          // this lane's column, unwrapped
     const int32_t col = region_coord(cx, g.nx, g.periodic[0]);  // -1 beyond a wall
-    const uint32_t ucol = col < 0 ? 0u : (uint32_t)col;     // any in-domain column for dead lanes
-    const bool own_col = lane >= 2 && lane < 2 + kStripCols && cx < (int32_t)g.nx;
+    const uint32_t ucol = col < 0 ? 0u : (uint32_t)col;         // any in-domain column for dead lanes
+    const bool own_col = lane >= NS && lane < NS + W && cx < (int32_t)g.nx;
 
-    // Rings: NI input rows (a row is loaded D iterations before its first
-    // use), NS step t+1 rows; the loop is unrolled over U iterations so that
-    // every ring index is a compile-time constant.
-    constexpr int D = kStreamAhead, NI = D + 3, NS = NI % 3 == 0 ? 3 : NI, U = NI;
+    // Rings: NI input rows, R rows of each intermediate step; the loop is
+    // unrolled over U = NI iterations so that every ring index is a
+    // compile-time constant.
+    constexpr int NI = D + 3, RS = NI % 3 == 0 ? 3 : NI, U = NI;
     // rows a step never fills (beyond a wall) are only ever discarded by the
     // bounce-back selects; start them at zero so no value is indeterminate
-    R fin[NI][QF] = {}, gin[NI][QG] = {};  // input rows
-    R f1[NS][QF] = {}, g1[NS][QG] = {};    // step t+1 rows
+    R fin[NI][QF] = {}, gin[NI][QG] = {};          // input rows
+    R fs[NS - 1][RS][QF] = {}, gs[NS - 1][RS][QG] = {};  // rows of steps 1 .. NS-1
 
     // The loop body is straight-line: every iteration loads a row and
-    // computes both steps; rows outside the segment or beyond a wall use an
+    // computes every step; rows outside the segment or beyond a wall use an
     // in-domain stand-in row and are never stored.  (Branches around the
     // loads would leave paths on which a load is not waited for, after which
     // the compiler drains every outstanding load before the next row.)
@@ -822,59 +824,68 @@ void stream2_kernel(Stream2Args<St> a) {
     const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
     auto iteration = [&](auto slot, int32_t k) {
         constexpr int S = decltype(slot)::value;  // k mod U
-        // ring slot of what iteration k - j loaded (input) or computed (step t+1)
+        // ring slot of what iteration k - j loaded (input) or computed (a step)
         constexpr auto in = [](int j) { return ((S - j) % NI + NI) % NI; };
-        constexpr auto s1 = [](int j) { return ((S - j) % NS + NS) % NS; };
+        constexpr auto st = [](int j) { return ((S - j) % RS + RS) % RS; };
+        const int32_t yin = y0 - NS + k;
         // 1. issue the loads of input row yin (its slot held row yin - NI)
-        const int32_t yin = y0 - 2 + k;
-        const int32_t rin = region_coord(yin, g.ny, g.periodic[1]);
-        const uint32_t row_in = (uint32_t)(rin >= 0 ? rin : min(max(yin, 0), last));
-        const uint32_t node = ucol + g.nx * row_in;
-        const uint32_t bf = pop_at<QF>(node, 0), bg = pop_at<QG>(node, 0);
-        static_for<0, QF>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            fin[in(0)][i] = St::EF::dec(*elem<O32>(a.fsrc, bf + i * kTile));
-        });
-        static_for<0, QG>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            gin[in(0)][i] = St::EG::dec(*elem<O32>(a.gsrc, bg + i * kTile));
-        });
-        // 2. step t+2 on row y2 = y1 - 2 from the step t+1 rows y2 - 1, y2,
-        //    y2 + 1 (computed in iterations k-3, k-2, k-1); stored on the
-        //    strip's own columns for y0 <= y2 < y0 + rows
         {
-            const int32_t y2 = yin - 3 - D;
-            const bool on = own_col && y2 >= y0 && y2 < y0 + rows;
-            const uint32_t yy = (uint32_t)min(max(y2, 0), last);
+            const int32_t rin = region_coord(yin, g.ny, g.periodic[1]);
+            const uint32_t row_in = (uint32_t)(rin >= 0 ? rin : min(max(yin, 0), last));
+            const uint32_t node = ucol + g.nx * row_in;
+            const uint32_t bf = pop_at<QF>(node, 0), bg = pop_at<QG>(node, 0);
+            static_for<0, QF>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                fin[in(0)][i] = St::EF::dec(*elem<O32>(a.fsrc, bf + i * kTile));
+            });
+            static_for<0, QG>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                gin[in(0)][i] = St::EG::dec(*elem<O32>(a.gsrc, bg + i * kTile));
+            });
+        }
+        const int32_t y1 = yin - 1 - D;  // row of step 1; step j runs on row y1 - 2 (j - 1)
+        // 2. steps NS, ..., 2: step j on row yj from the rows yj - 1, yj,
+        //    yj + 1 of step j - 1 (computed in iterations k-3, k-2, k-1),
+        //    into the ring slot of step j that step j + 1 has just read
+        static_for<0, NS - 1>([&](auto jc) {
+            constexpr int j = NS - decltype(jc)::value;  // NS, NS-1, ..., 2
+            const int32_t yj = y1 - 2 * (j - 1);
+            const bool own = own_col && yj >= y0 && yj < y0 + rows;
+            const uint32_t yy = (uint32_t)min(max(yj, 0), last);
             const uint32_t x = own_col ? (uint32_t)cx : ucol;
             const Neighbours nb = neighbours(g, x, yy, 0);
-            const RegSrc<St, QF, QG> src{f1[s1(3)], f1[s1(2)], f1[s1(1)], g1[s1(3)], g1[s1(2)], g1[s1(1)]};
-            if constexpr (O32) {
-                const OwnedBufDst<St, QF, QG> dst(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, on);
-                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot2, on});
+            const RegSrc<St, QF, QG> src{fs[j - 2][st(3)], fs[j - 2][st(2)], fs[j - 2][st(1)],
+                                         gs[j - 2][st(3)], gs[j - 2][st(2)], gs[j - 2][st(1)]};
+            const PtrFlux2 fx{a.flux, a.slot[(a.t_parity + j) & 1], own};
+            if constexpr (j == NS) {
+                if constexpr (O32) {
+                    const OwnedBufDst<St, QF, QG> dst(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, own);
+                    step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                } else {
+                    const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, own);
+                    step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                }
             } else {
-                const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, on);
-                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot2, on});
+                const RegDst<St, QF, QG> dst{fs[j - 1][st(0)], gs[j - 1][st(0)]};
+                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, fx);
             }
-        }
-        // 3. step t+1 on row y1 = yin - 1 - D from the input rows y1 - 1, y1,
-        //    y1 + 1 (loaded in iterations k-2-D, k-1-D, k-D), into the slot
-        //    step 2 has just read its row y2 - 1 from
+        });
+        // 3. step 1 on row y1 from the input rows y1 - 1, y1, y1 + 1 (loaded in
+        //    iterations k-2-D, k-1-D, k-D), into the slot step 2 has just read
         {
-            const int32_t y1 = yin - 1 - D;
             const int32_t r1 = region_coord(y1, g.ny, g.periodic[1]);
             const uint32_t yy = (uint32_t)(r1 >= 0 ? r1 : min(max(y1, 0), last));
             const Neighbours nb = neighbours(g, ucol, yy, 0);
             const RegSrc<St, QF, QG> src{fin[in(2 + D)], fin[in(1 + D)], fin[in(D)],
                                          gin[in(2 + D)], gin[in(1 + D)], gin[in(D)]};
-            const RegDst<St, QF, QG> dst{f1[s1(0)], g1[s1(0)]};
+            const RegDst<St, QF, QG> dst{fs[0][st(0)], gs[0][st(0)]};
             const bool own = own_col && y1 >= y0 && y1 < y0 + rows;
-            step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot1, own});
+            step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot[(a.t_parity + 1) & 1], own});
         }
     };
-    // iterations k = 0 .. rows + 4 + D carry the segment; the count is
-    // rounded up to whole groups of U (the extra ones store nothing)
-    for (int32_t k = 0; k < rows + 5 + D; k += U) {
+    // step NS reaches row y0 + rows - 1 at k = rows + 3 NS - 2 + D; the
+    // count is rounded up to whole groups of U (the extra ones store nothing)
+    for (int32_t k = 0; k < rows + 3 * NS - 1 + D; k += U) {
         static_for<0, U>([&](auto sc) { iteration(sc, k + decltype(sc)::value); });
     }
 }

@@ -403,6 +403,19 @@ lbm_status face_sums(lbm_ctx* c, double* host12) {
 
 namespace {
 
+// Steps per launch a 2D context starts with: the fastest measured on the
+// 8193^2 cell per storage mode (GLUPS at 1/2/3/4 steps: FP32 51/59/86/110,
+// FP16-f+FP32-g 74/81/109/104, FP16 104/103/104/100, BF16 98/110/107/88,
+// FP64 25/35/20/-; deeper launches spill registers in FP64 and BF16).
+int32_t default_steps_per_launch(int32_t storage) {
+    switch (storage) {
+    case LBM_FP32: return 4;
+    case LBM_MIXED_F16_G32: return 3;
+    case LBM_FP16_SHIFTED: return 3;
+    default: return 2;  // FP64, BF16
+    }
+}
+
 // every population array is under 4 GiB: 32-bit byte offsets suffice
 bool fits_o32(const lbm_ctx* c) {
     const size_t Np = ((size_t)c->geo.N + kTile - 1) / kTile * kTile;
@@ -416,14 +429,19 @@ bool fits_o32(const lbm_ctx* c) {
 #ifndef LBM_STREAM_WAVES
 #define LBM_STREAM_WAVES 4
 #endif
+#ifndef LBM_STREAM_AHEAD
+#define LBM_STREAM_AHEAD 1  // rows between a row's loads and their first use (two-step kernel)
+#endif
 
-// k launches of the register-row two-step kernel, A -> B, advancing t by 2k
-template <class St> void stream2_launches(lbm_ctx* c, int64_t k) {
+// k launches of the register-row kernel of NS steps each (prefetch distance
+// D rows), A -> B, advancing t by NS k
+template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
     constexpr int NWB = LBM_STREAM_WAVES;
-    Stream2Args<St> a{};
+    constexpr uint32_t W = strip_cols<NS>();
+    StreamArgs<St> a{};
     a.geo = c->geo;
     a.c = make_coef<typename St::R>(c);
-    a.strips = (c->geo.nx + kStripCols - 1) / kStripCols;
+    a.strips = (c->geo.nx + W - 1) / W;
     a.seg_rows = LBM_STREAM_ROWS;
     a.units = a.strips * ((c->geo.ny + a.seg_rows - 1) / a.seg_rows);
     const uint32_t blocks = (a.units + NWB - 1) / NWB;
@@ -434,18 +452,19 @@ template <class St> void stream2_launches(lbm_ctx* c, int64_t k) {
     a.f_bytes = o32 ? (uint32_t)(Np * Flow<2>::Q * sizeof(typename St::TF)) : 0u;
     a.g_bytes = o32 ? (uint32_t)(Np * Heat<2>::Q * sizeof(typename St::TG)) : 0u;
     a.flux = c->flux(0, 0);
+    a.slot[0] = 0;
+    a.slot[1] = (uint32_t)c->lay.flux_doubles;
     for (int64_t s = 0; s < k; ++s) {
         const auto A = pops<St>(c, c->cur), B = pops<St>(c, 1 - c->cur);
         a.fsrc = A.f;
         a.gsrc = A.g;
         a.fdst = B.f;
         a.gdst = B.g;
-        a.slot1 = (uint32_t)(((c->t + 1) & 1) * c->lay.flux_doubles);
-        a.slot2 = (uint32_t)(((c->t + 2) & 1) * c->lay.flux_doubles);
-        if (o32) hipLaunchKernelGGL((stream2_kernel<St, NWB, true>), grid, block, 0, c->stream, a);
-        else hipLaunchKernelGGL((stream2_kernel<St, NWB, false>), grid, block, 0, c->stream, a);
+        a.t_parity = (int32_t)(c->t & 1);
+        if (o32) hipLaunchKernelGGL((stream_kernel<St, NWB, true, NS, D>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((stream_kernel<St, NWB, false, NS, D>), grid, block, 0, c->stream, a);
         c->cur = 1 - c->cur;
-        c->t += 2;
+        c->t += NS;
     }
 }
 
@@ -507,7 +526,7 @@ lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void
     c->ws = (char*)d_workspace;
     c->cur = 0;
     c->t = -1;
-    c->steps_per_launch = p->dim == 2 && !view ? 2 : 1;
+    c->steps_per_launch = p->dim == 2 && !view ? default_steps_per_launch(p->storage) : 1;
     Geometry& g = c->geo;
     g.nx = p->n[0];
     g.ny = p->n[1];
@@ -622,8 +641,16 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         constexpr int DIM = decltype(dimc)::value;
         using St = decltype(stc);
         if constexpr (DIM == 2) {
-            if (c->steps_per_launch == 2 && n >= 2) {
-                stream2_launches<St>(c, n / 2);
+            if (c->steps_per_launch == 4 && n >= 4) {
+                stream_launches<St, 4, 0>(c, n / 4);
+                n -= n / 4 * 4;
+            }
+            if (c->steps_per_launch >= 3 && n >= 3) {
+                stream_launches<St, 3, 0>(c, n / 3);
+                n -= n / 3 * 3;
+            }
+            if (c->steps_per_launch >= 2 && n >= 2) {
+                stream_launches<St, 2, LBM_STREAM_AHEAD>(c, n / 2);
                 n -= n / 2 * 2;
             }
         }
@@ -652,9 +679,9 @@ lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps) {
     lbm_status st = enter(c);
     if (st) return st;
     if (c->view) return reject_view(c, "lbm_set_steps_per_launch");
-    if (steps != 1 && steps != 2) return set_err(c->err, LBM_E_INVALID, "steps per launch must be 1 or 2");
-    if (steps == 2 && c->p.dim != 2)
-        return set_err(c->err, LBM_E_UNSUPPORTED, "two steps per launch are implemented in 2D only");
+    if (steps < 1 || steps > 4) return set_err(c->err, LBM_E_INVALID, "steps per launch must lie in 1 .. 4");
+    if (steps > 1 && c->p.dim != 2)
+        return set_err(c->err, LBM_E_UNSUPPORTED, "several steps per launch are implemented in 2D only");
     c->steps_per_launch = steps;
     return LBM_OK;
 }

@@ -268,7 +268,8 @@ class Cavity:
 
     @property
     def steps_per_launch(self) -> int:
-        """Steps per kernel launch of step(): 1, or 2 (2D, the default)."""
+        """Steps per kernel launch of step(): 1 .. 4 (above 1 in 2D only; a 2D
+        cavity starts with the fastest count for its storage mode)."""
         return int(lib().lbm_get_steps_per_launch(self._h))
 
     @steps_per_launch.setter

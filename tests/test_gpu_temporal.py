@@ -1,13 +1,14 @@
-"""Two steps per launch (2D temporal blocking) against one step per launch.
+"""Two to four steps per launch (2D temporal blocking) against one step
+per launch.
 
-The two-step kernel applies the same per-node update to the same stored
+The streaming kernels apply the same per-node update to the same stored
 values (the intermediate rows stay in registers, rounded through the storage
 type), so the whole exported state -- populations, both wall-flux slots and
 t -- must be bitwise identical, in every storage mode and boundary layout,
 including grids narrower than one strip, grids whose rows wrap more than
-once, ragged strips and segments, and an odd step count (which ends with a
-single-step launch).  Parity of the default (two-step) path with the
-oracle is covered by test_gpu_parity."""
+once, ragged strips and segments, and step counts that the steps per launch
+do not divide (which end with shorter launches).  Parity of the default
+(two-step) path with the oracle is covered by test_gpu_parity."""
 import numpy as np
 import pytest
 
@@ -38,19 +39,24 @@ def _run(cfg, spl, steps, seed=9, amp=2e-2):
 
 @pytest.mark.parametrize("storage", STORAGES)
 @pytest.mark.parametrize("shape", SHAPES)
-def test_two_step_bitwise(storage, shape):
+def test_multi_step_bitwise(storage, shape):
+    """23 steps: 11 launches of two + one single step, 7 of three + one of
+    two, 5 of four + one of three, against 23 single steps."""
     for name, cfg in _layouts(shape, storage).items():
         if name != "box" and min(shape) < 2:
             continue  # a walled axis needs two nodes
         one = _run(cfg, 1, 23)
-        two = _run(cfg, 2, 23)
-        assert one.t == two.t == 23
-        a, b = one.export_state(), two.export_state()
-        assert len(a) == len(b)
-        if a != b:
-            x, y = np.frombuffer(a, np.uint8), np.frombuffer(b, np.uint8)
-            bad = np.flatnonzero(x != y)
-            pytest.fail(f"{name} {shape} {storage}: {bad.size} bytes differ, first at {bad[:8]}")
+        a = one.export_state()
+        for spl in (2, 3, 4):
+            other = _run(cfg, spl, 23)
+            assert one.t == other.t == 23
+            b = other.export_state()
+            assert len(a) == len(b)
+            if a != b:
+                x, y = np.frombuffer(a, np.uint8), np.frombuffer(b, np.uint8)
+                bad = np.flatnonzero(x != y)
+                pytest.fail(f"{name} {shape} {storage}, {spl} steps per launch: {bad.size} bytes differ, "
+                            f"first at {bad[:8]}")
 
 
 def test_two_step_after_single_steps_and_nusselt():
@@ -58,38 +64,44 @@ def test_two_step_after_single_steps_and_nusselt():
     cfg = W.rayleigh_benard(2, (257, 129), ra=1e5, pr=0.71, storage="fp32")
     ref = _run(cfg, 1, 0)
     mix = _run(cfg, 1, 0)
-    for n in (3, 4, 1, 6, 5):
+    for n, spl in ((3, 2), (4, 1), (1, 3), (6, 3), (5, 2), (7, 4), (9, 3), (4, 4)):
         ref.step(n)
-        mix.steps_per_launch = 2 if mix.steps_per_launch == 1 else 1
+        mix.steps_per_launch = spl
         mix.step(n)
     assert ref.export_state() == mix.export_state()
     assert ref.nusselt() == mix.nusselt()
 
 
 def test_steps_per_launch_arguments():
+    defaults = {"fp32": 4, "mixed": 3, "fp16": 3, "bf16": 2, "fp64": 2}
+    for st, k in defaults.items():
+        assert lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage=st)).steps_per_launch == k
     c2 = lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage="fp32"))
-    assert c2.steps_per_launch == 2
-    for bad in (0, 3, -1):
+    for bad in (0, 5, -1):
         with pytest.raises(lbm.LBMError) as e:
             c2.steps_per_launch = bad
         assert e.value.status == -1
     c3 = lbm.Cavity(W.rayleigh_benard(3, (9, 9, 9), ra=1e4, pr=0.71, storage="fp32"))
     assert c3.steps_per_launch == 1
-    with pytest.raises(lbm.LBMError) as e:
-        c3.steps_per_launch = 2
-    assert e.value.status == -5
+    for k in (2, 3, 4):
+        with pytest.raises(lbm.LBMError) as e:
+            c3.steps_per_launch = k
+        assert e.value.status == -5
     c3.steps_per_launch = 1
+    c2.steps_per_launch = 3
+    assert c2.steps_per_launch == 3
 
 
-def test_two_step_beyond_4gib_arrays():
+def test_multi_step_beyond_4gib_arrays():
     """FP64 8193^2: each population array exceeds 4 GiB, which takes the
-    two-step kernel's 64-bit addressing path (plain stores under a branch
-    instead of buffer stores).  Moments and wall fluxes must agree bitwise."""
+    streaming kernels' 64-bit addressing path (plain stores under a branch
+    instead of buffer stores).  Moments and wall fluxes must agree bitwise
+    after 5 steps with one to four steps per launch."""
     import torch
     cfg = W.rayleigh_benard(2, (8193, 8193), ra=1e8, pr=0.71, storage="fp64")
     res = []
-    for spl in (1, 2):
-        c = _run(cfg, spl, 3, amp=1e-3)
+    for spl in (1, 2, 3, 4):
+        c = _run(cfg, spl, 5, amp=1e-3)
         n = c.N
         rho = torch.empty(n, dtype=torch.float64, device="cuda")
         u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
@@ -98,6 +110,7 @@ def test_two_step_beyond_4gib_arrays():
         res.append((rho, u, T, c.wall_flux()))
         del c
         torch.cuda.empty_cache()
-    (r1, u1, t1, w1), (r2, u2, t2, w2) = res
-    assert torch.equal(r1, r2) and torch.equal(u1, u2) and torch.equal(t1, t2)
-    assert all(np.array_equal(a, b) for a, b in zip(w1, w2))
+    (r1, u1, t1, w1) = res[0]
+    for (r2, u2, t2, w2) in res[1:]:
+        assert torch.equal(r1, r2) and torch.equal(u1, u2) and torch.equal(t1, t2)
+        assert all(np.array_equal(a, b) for a, b in zip(w1, w2))
