@@ -568,9 +568,11 @@ __device__ __forceinline__ GlobalSrc<St, QF, QG, O32> global_src(const Geometry&
 
 // One fused update of the node at (x, y, z): pull from `src` with the wall
 // rules, moments, both collisions, store to `dst`; the wall heat flux of
-// the node's Dirichlet links goes to the flux sink `fx`.
+// the node's Dirichlet links goes to the flux sink `fx`.  Walls = false is
+// for nodes known to have every link inside the domain (or across a
+// periodic face): it drops the wall rules and the flux at compile time.
 // Returns false if the new rho or T is not finite.
-template <int DIM, class St, class Src, class Dst, class Flux>
+template <int DIM, class St, bool Walls = true, class Src, class Dst, class Flux>
 __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename St::R>& c, const Neighbours& nb,
                                           uint32_t x, uint32_t y, uint32_t z, const Src& src, const Dst& dst,
                                           const Flux& fx) {
@@ -585,8 +587,8 @@ __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
-        const bool out = (ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
-                         (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp);
+        const bool out = Walls && ((ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
+                                   (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp));
         hf[i] = src.template pull_f<i, ex, ey, ez, L::opp[i]>(out);
     });
     R wall_v[H::Q];
@@ -597,8 +599,8 @@ __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename
         // the wall a crossing link meets: axis of e_i, the side it comes from
         constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
         constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
-        const bool out = (ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
-                         (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp);
+        const bool out = Walls && ((ex > 0 && !nb.okxm) || (ex < 0 && !nb.okxp) || (ey > 0 && !nb.okym) ||
+                                   (ey < 0 && !nb.okyp) || (ez > 0 && !nb.okzm) || (ez < 0 && !nb.okzp));
         const R v = src.template pull_g<i, ex, ey, ez, H::opp[i]>(out);
         // anti-bounce-back on a Dirichlet wall, plain bounce-back (adiabatic)
         // otherwise
@@ -606,14 +608,15 @@ __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename
         wall_v[i] = v;
         hg[i] = wall_abb[i] ? c.abb[face] - v : v;
     });
-    static_for<1, H::Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        constexpr int ex = H::ex[i], ey = H::ey[i], ez = H::ez[i];
-        constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
-        constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
-        const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
-        fx.template put<face>(g, local, c.abb_d[face] - 2.0 * (double)wall_v[i], wall_abb[i]);
-    });
+    if constexpr (Walls)
+        static_for<1, H::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int ex = H::ex[i], ey = H::ey[i], ez = H::ez[i];
+            constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
+            constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
+            const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
+            fx.template put<face>(g, local, c.abb_d[face] - 2.0 * (double)wall_v[i], wall_abb[i]);
+        });
     return collide_store<DIM, St>(hf, hg, c, dst);
 }
 
@@ -822,8 +825,9 @@ void stream_kernel(StreamArgs<St> a) {
     // the compiler drains every outstanding load before the next row.)
     const int32_t last = (int32_t)g.ny - 1;
     const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
-    auto iteration = [&](auto slot, int32_t k) {
+    auto iteration = [&](auto slot, auto walls, int32_t k) {
         constexpr int S = decltype(slot)::value;  // k mod U
+        constexpr bool Wl = decltype(walls)::value;
         // ring slot of what iteration k - j loaded (input) or computed (a step)
         constexpr auto in = [](int j) { return ((S - j) % NI + NI) % NI; };
         constexpr auto st = [](int j) { return ((S - j) % RS + RS) % RS; };
@@ -860,14 +864,14 @@ void stream_kernel(StreamArgs<St> a) {
             if constexpr (j == NS) {
                 if constexpr (O32) {
                     const OwnedBufDst<St, QF, QG> dst(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, own);
-                    step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                    step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
                 } else {
                     const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, own);
-                    step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                    step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
                 }
             } else {
                 const RegDst<St, QF, QG> dst{fs[j - 1][st(0)], gs[j - 1][st(0)]};
-                step_node<2, St>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
             }
         });
         // 3. step 1 on row y1 from the input rows y1 - 1, y1, y1 + 1 (loaded in
@@ -880,14 +884,28 @@ void stream_kernel(StreamArgs<St> a) {
                                          gin[in(2 + D)], gin[in(1 + D)], gin[in(D)]};
             const RegDst<St, QF, QG> dst{fs[0][st(0)], gs[0][st(0)]};
             const bool own = own_col && y1 >= y0 && y1 < y0 + rows;
-            step_node<2, St>(g, a.c, nb, ucol, yy, 0u, src, dst, PtrFlux2{a.flux, a.slot[(a.t_parity + 1) & 1], own});
+            step_node<2, St, Wl>(g, a.c, nb, ucol, yy, 0u, src, dst,
+                                 PtrFlux2{a.flux, a.slot[(a.t_parity + 1) & 1], own});
         }
     };
     // step NS reaches row y0 + rows - 1 at k = rows + 3 NS - 2 + D; the
     // count is rounded up to whole groups of U (the extra ones store nothing)
-    for (int32_t k = 0; k < rows + 3 * NS - 1 + D; k += U) {
-        static_for<0, U>([&](auto sc) { iteration(sc, k + decltype(sc)::value); });
-    }
+    auto sweep = [&](auto walls) {
+        for (int32_t k = 0; k < rows + 3 * NS - 1 + D; k += U) {
+            static_for<0, U>([&](auto sc) { iteration(sc, walls, k + decltype(sc)::value); });
+        }
+    };
+    // Every update that feeds a stored result lies on lanes 1 .. 62 of step
+    // 1 (columns x0 - NS + 1 .. x0 - NS + 62) and in its rows y0 - (NS - 1)
+    // .. y0 + rows - 1 + (NS - 1).  When all of those nodes are at least one
+    // node from every non-periodic wall, no link of theirs crosses a wall,
+    // and the wavefront runs the sweep without wall rules and wall flux.
+    const bool inner_x = g.periodic[0] || (x0 - NS + 1 >= 1 && x0 - NS + 62 <= (int32_t)g.nx - 2);
+    const bool inner_y = g.periodic[1] || (y0 - (NS - 1) >= 1 && y0 + rows - 1 + (NS - 1) <= (int32_t)g.ny - 2);
+    if (inner_x && inner_y)
+        sweep(std::false_type{});
+    else
+        sweep(std::true_type{});
 }
 
 // --------------------------------------------------------- batched cavities

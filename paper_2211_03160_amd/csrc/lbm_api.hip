@@ -404,15 +404,14 @@ lbm_status face_sums(lbm_ctx* c, double* host12) {
 namespace {
 
 // Steps per launch a 2D context starts with: the fastest measured on the
-// 8193^2 cell per storage mode (GLUPS at 1/2/3/4 steps: FP32 51/59/86/110,
-// FP16-f+FP32-g 74/81/109/104, FP16 104/103/104/100, BF16 98/110/107/88,
-// FP64 25/35/20/-; deeper launches spill registers in FP64 and BF16).
+// 8193^2 cell per storage mode (GLUPS at 1/2/3/4 steps: FP32 51/57/86/110,
+// FP16-f+FP32-g 74/80/119/119, FP16 103/103/121/116, BF16 99/104/124/103,
+// FP64 25/34/28/18; deeper FP64 launches run short of registers).
 int32_t default_steps_per_launch(int32_t storage) {
     switch (storage) {
     case LBM_FP32: return 4;
-    case LBM_MIXED_F16_G32: return 3;
-    case LBM_FP16_SHIFTED: return 3;
-    default: return 2;  // FP64, BF16
+    case LBM_FP64: return 2;
+    default: return 3;  // FP16, BF16, FP16-f+FP32-g
     }
 }
 

@@ -7,8 +7,9 @@ type), so the whole exported state -- populations, both wall-flux slots and
 t -- must be bitwise identical, in every storage mode and boundary layout,
 including grids narrower than one strip, grids whose rows wrap more than
 once, ragged strips and segments, and step counts that the steps per launch
-do not divide (which end with shorter launches).  Parity of the default
-(two-step) path with the oracle is covered by test_gpu_parity."""
+do not divide (which end with shorter launches), and tall grids whose
+inner segments take the sweep without wall rules.  Parity of the default
+(two-step) path with the oracle is covered by test_gpu_parity.
 import numpy as np
 import pytest
 
@@ -17,7 +18,10 @@ from paper_2211_03160_amd import lbm, workloads as W
 pytestmark = pytest.mark.gpu
 
 STORAGES = ["fp32", "fp64", "fp16", "bf16", "mixed"]
-SHAPES = [(129, 129), (67, 45), (64, 19), (65, 20), (5, 7), (2, 2), (300, 3), (7, 200), (1, 33), (40, 1)]
+# (70, 1000) has segments clear of both walls next to ones that touch them,
+# so wavefronts run both the wall-free and the general sweep
+SHAPES = [(129, 129), (67, 45), (64, 19), (65, 20), (5, 7), (2, 2), (300, 3), (7, 200), (1, 33), (40, 1),
+          (70, 1000)]
 
 
 def _layouts(shape, storage):
@@ -73,7 +77,7 @@ def test_two_step_after_single_steps_and_nusselt():
 
 
 def test_steps_per_launch_arguments():
-    defaults = {"fp32": 4, "mixed": 3, "fp16": 3, "bf16": 2, "fp64": 2}
+    defaults = {"fp32": 4, "mixed": 3, "fp16": 3, "bf16": 3, "fp64": 2}
     for st, k in defaults.items():
         assert lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage=st)).steps_per_launch == k
     c2 = lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage="fp32"))
