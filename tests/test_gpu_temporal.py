@@ -9,7 +9,7 @@ including grids narrower than one strip, grids whose rows wrap more than
 once, ragged strips and segments, and step counts that the steps per launch
 do not divide (which end with shorter launches), and tall grids whose
 inner segments take the sweep without wall rules.  Parity of the default
-(two-step) path with the oracle is covered by test_gpu_parity.
+(multi-step) path with the oracle is covered by test_gpu_parity."""
 import numpy as np
 import pytest
 
