@@ -29,7 +29,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "GLUPS & %HBM peak, FP32 vs FP16-store, 8193² D2Q9+D2Q5 / 385³ D3Q19+D3Q7"
-KERNEL_SOURCES = ["paper_2211_03160_amd/csrc/kernels.hpp", "paper_2211_03160_amd/csrc/lattice.hpp"]
+# the kernels and their launch configuration (strip segments, steps per
+# launch): HBM traffic counters are valid for this hash only
+KERNEL_SOURCES = ["paper_2211_03160_amd/csrc/kernels.hpp", "paper_2211_03160_amd/csrc/lattice.hpp",
+                  "paper_2211_03160_amd/csrc/lbm_api.hip"]
 TRAFFIC_FILES = {4: os.path.join(ROOT, "profiles", "stream4_d2q9_fp32_8193_counters.txt"),
                  1: os.path.join(ROOT, "profiles", "step_d2q9_fp32_8193_counters.txt")}
 # FP32 operations per 2D lattice update in the kernels' formulation (adds,

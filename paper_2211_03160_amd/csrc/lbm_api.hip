@@ -422,9 +422,6 @@ bool fits_o32(const lbm_ctx* c) {
     return Np * qf_of(c->p.dim) * elem_f(c->p.storage) < lim && Np * qg_of(c->p.dim) * elem_g(c->p.storage) < lim;
 }
 
-#ifndef LBM_STREAM_ROWS
-#define LBM_STREAM_ROWS 128
-#endif
 #ifndef LBM_STREAM_WAVES
 #define LBM_STREAM_WAVES 4
 #endif
@@ -434,6 +431,21 @@ bool fits_o32(const lbm_ctx* c) {
 
 // k launches of the register-row kernel of NS steps each (prefetch distance
 // D rows), A -> B, advancing t by NS k
+// Rows per strip segment (one wavefront each), by storage and steps per
+// launch, measured on the 8193^2 cell.  Launches that move many bytes per
+// update run fastest with short segments even though every segment repeats
+// the 3 NS - 1 rows that fill the step pipeline (FP32 at three steps: 107 /
+// 99 / 91 GLUPS at 16 / 32 / 64 rows; FP64 at two: 38 / 35 / 35); the
+// four-step FP32 launch peaks at 40 (120 / 127 / 122 at 32 / 40 / 64) and
+// the 16-bit ones at about 64 (mixed 110 / 119 / 124 at 32 / 48 / 64).
+template <class St, int NS> constexpr uint32_t stream_seg_rows() {
+    constexpr bool f32 = sizeof(typename St::TF) == 4 && sizeof(typename St::TG) == 4;
+    constexpr bool f64 = sizeof(typename St::TF) == 8;
+    if constexpr (f64) return NS == 2 ? 16 : 64;
+    else if constexpr (f32) return NS == 4 ? 40 : 16;
+    else return 64;
+}
+
 template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
     constexpr int NWB = LBM_STREAM_WAVES;
     constexpr uint32_t W = strip_cols<NS>();
@@ -441,7 +453,7 @@ template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
     a.geo = c->geo;
     a.c = make_coef<typename St::R>(c);
     a.strips = (c->geo.nx + W - 1) / W;
-    a.seg_rows = LBM_STREAM_ROWS;
+    a.seg_rows = stream_seg_rows<St, NS>();
     a.units = a.strips * ((c->geo.ny + a.seg_rows - 1) / a.seg_rows);
     const uint32_t blocks = (a.units + NWB - 1) / NWB;
     a.blocks_per_xcd = (blocks + kXcd - 1) / kXcd;
