@@ -172,7 +172,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
 /* Steps per kernel launch of lbm_step: 1 .. 4 (more than 1 in 2D only).
  * A 2D context starts with the count measured fastest for its storage:
- * 4 (FP32), 3 (FP16, BF16, FP16-f+FP32-g), 2 (FP64); 3D contexts with 1.
+ * 4 (FP32, FP16-f+FP32-g), 3 (FP16, BF16), 2 (FP64); 3D contexts with 1.
  * With k > 1, each wavefront walks down a strip of
  * columns row by row, keeping the last rows of step t and of the
  * intermediate steps in registers, and writes step t+k: the update of every

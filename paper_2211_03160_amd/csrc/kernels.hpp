@@ -778,15 +778,18 @@ template <class St> struct StreamArgs {
     uint32_t blocks_per_xcd;
 };
 
-// Register budget: three wavefronts per SIMD (168 registers) with FP32
-// arithmetic and two steps, two with three steps or FP64, whose rows take
-// more registers.  (At four, 128 registers, the two-step FP32 kernel spills
-// and runs slower.)
+// Register budget (measured): three wavefronts per SIMD (168 registers) for
+// two steps, and for three steps when f and g are both 16-bit (a small
+// spill, outweighed by the third wavefront); two (256 registers) for four
+// steps, for three steps with FP32 populations, and for FP64 arithmetic.
 #ifndef LBM_STREAM_WAVES_PER_SIMD
 #define LBM_STREAM_WAVES_PER_SIMD 3
 #endif
 template <class St, int NS> constexpr int stream_waves_per_simd() {
-    return sizeof(typename St::R) == 8 || NS > 2 ? 2 : LBM_STREAM_WAVES_PER_SIMD;
+    constexpr bool half = sizeof(typename St::TF) == 2 && sizeof(typename St::TG) == 2;
+    if constexpr (sizeof(typename St::R) == 8 || NS > 3) return 2;
+    else if constexpr (NS == 3) return half ? LBM_STREAM_WAVES_PER_SIMD : 2;
+    else return LBM_STREAM_WAVES_PER_SIMD;
 }
 
 template <class St, int NWB, bool O32, int NS, int D>
@@ -825,6 +828,17 @@ void stream_kernel(StreamArgs<St> a) {
     // the compiler drains every outstanding load before the next row.)
     const int32_t last = (int32_t)g.ny - 1;
     const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
+    // Row y of step j < NS feeds a stored result only inside the dependency
+    // cone of the segment, rows y0 - (NS - j) .. y0 + rows - 1 + (NS - j);
+    // elsewhere (while the step pipeline fills and drains) the step is
+    // skipped by a wavefront-uniform branch, and nothing needed reads the
+    // ring slot it would have written.  Step NS always runs: a branch around
+    // its stores would make the compiler wait for them before later loads.
+    // (FP64 arithmetic keeps every step: the branches cost it registers.)
+    auto needed = [&](int j, int32_t y) {
+        const int32_t rel = y - y0;
+        return sizeof(R) == 8 || (rel >= -(NS - j) && rel <= rows - 1 + (NS - j));
+    };
     auto iteration = [&](auto slot, auto walls, int32_t k) {
         constexpr int S = decltype(slot)::value;  // k mod U
         constexpr bool Wl = decltype(walls)::value;
@@ -869,14 +883,14 @@ void stream_kernel(StreamArgs<St> a) {
                     const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, own);
                     step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
                 }
-            } else {
+            } else if (needed(j, yj)) {
                 const RegDst<St, QF, QG> dst{fs[j - 1][st(0)], gs[j - 1][st(0)]};
                 step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
             }
         });
         // 3. step 1 on row y1 from the input rows y1 - 1, y1, y1 + 1 (loaded in
         //    iterations k-2-D, k-1-D, k-D), into the slot step 2 has just read
-        {
+        if (needed(1, y1)) {
             const int32_t r1 = region_coord(y1, g.ny, g.periodic[1]);
             const uint32_t yy = (uint32_t)(r1 >= 0 ? r1 : min(max(y1, 0), last));
             const Neighbours nb = neighbours(g, ucol, yy, 0);

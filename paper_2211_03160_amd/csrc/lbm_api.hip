@@ -404,14 +404,15 @@ lbm_status face_sums(lbm_ctx* c, double* host12) {
 namespace {
 
 // Steps per launch a 2D context starts with: the fastest measured on the
-// 8193^2 cell per storage mode (GLUPS at 1/2/3/4 steps: FP32 51/57/86/110,
-// FP16-f+FP32-g 74/80/119/119, FP16 103/103/121/116, BF16 99/104/124/103,
-// FP64 25/34/28/18; deeper FP64 launches run short of registers).
+// 8193^2 cell per storage mode (GLUPS at 1/2/3/4 steps, each with its best
+// segment length: FP32 51/69/113/137, FP16-f+FP32-g 74/98/146/155, FP16
+// 103/125/152/153, BF16 99/119/136/110, FP64 25/38/30/-).
 int32_t default_steps_per_launch(int32_t storage) {
     switch (storage) {
     case LBM_FP32: return 4;
+    case LBM_MIXED_F16_G32: return 4;
     case LBM_FP64: return 2;
-    default: return 3;  // FP16, BF16, FP16-f+FP32-g
+    default: return 3;  // FP16, BF16
     }
 }
 
@@ -433,17 +434,21 @@ bool fits_o32(const lbm_ctx* c) {
 // D rows), A -> B, advancing t by NS k
 // Rows per strip segment (one wavefront each), by storage and steps per
 // launch, measured on the 8193^2 cell.  Launches that move many bytes per
-// update run fastest with short segments even though every segment repeats
-// the 3 NS - 1 rows that fill the step pipeline (FP32 at three steps: 107 /
-// 99 / 91 GLUPS at 16 / 32 / 64 rows; FP64 at two: 38 / 35 / 35); the
-// four-step FP32 launch peaks at 40 (120 / 127 / 122 at 32 / 40 / 64) and
-// the 16-bit ones at about 64 (mixed 110 / 119 / 124 at 32 / 48 / 64).
+// update run fastest with short segments, even though the first and last
+// rows of every segment repeat part of the dependency cone (FP32 at three
+// steps: 115 / 104 / 96 GLUPS at 16 / 32 / 64 rows; FP64 at two: 38 / 35 /
+// 35); FP32 at four steps peaks at 24 (134 / 139 / 137 / 124 at 16 / 24 /
+// 32 / 64), FP16-f+FP32-g at four near 64-80 (139 / 151 / 152 / 155 / 146
+// at 24 / 48 / 64 / 80 / 128) and FP16 / BF16 at three near 40-64 (FP16
+// 141 / 155 / 154 at 16 / 40 / 64, BF16 122 / 138 / 140).
 template <class St, int NS> constexpr uint32_t stream_seg_rows() {
     constexpr bool f32 = sizeof(typename St::TF) == 4 && sizeof(typename St::TG) == 4;
     constexpr bool f64 = sizeof(typename St::TF) == 8;
+    constexpr bool half = sizeof(typename St::TF) == 2 && sizeof(typename St::TG) == 2;
     if constexpr (f64) return NS == 2 ? 16 : 64;
-    else if constexpr (f32) return NS == 4 ? 40 : 16;
-    else return 64;
+    else if constexpr (f32) return NS == 4 ? 24 : 16;
+    else if constexpr (half) return NS == 2 ? 40 : NS == 3 ? 48 : 64;
+    else return NS == 2 ? 16 : NS == 3 ? 40 : 64;  // FP16 f, FP32 g
 }
 
 template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {

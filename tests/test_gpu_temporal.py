@@ -77,7 +77,7 @@ def test_two_step_after_single_steps_and_nusselt():
 
 
 def test_steps_per_launch_arguments():
-    defaults = {"fp32": 4, "mixed": 3, "fp16": 3, "bf16": 3, "fp64": 2}
+    defaults = {"fp32": 4, "mixed": 4, "fp16": 3, "bf16": 3, "fp64": 2}
     for st, k in defaults.items():
         assert lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage=st)).steps_per_launch == k
     c2 = lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage="fp32"))
