@@ -116,7 +116,10 @@ struct Geometry {
 };
 
 // Relaxation rates are indexed by row kind (RowKind), not by row: rows of
-// one kind share a rate, so a kernel holds only the distinct values.
+// one kind share a rate, so a kernel holds only the distinct values.  Where
+// every kind's rows also share |M_k|^2 (2D), s, b and q come divided by it,
+// which saves the scaling of each relaxed moment before the inverse
+// transform (folded_rates).
 template <class R> struct Coef {
     R s[10];     // flow rate per row kind (0 on conserved kinds)
     R b[10];     // 1 - s/2 per row kind
@@ -128,6 +131,11 @@ template <class R> struct Coef {
     R abb[6];    // omega (T_w - T_b) on Dirichlet faces
     double abb_d[6];  // the same in FP64, for the wall heat flux
 };
+
+template <int DIM> constexpr bool folded_rates() {
+    return kinds_share_norm<Flow<DIM>>() && kinds_share_norm<Heat<DIM>>();
+}
+static_assert(folded_rates<2>() && !folded_rates<3>(), "2D rates carry 1/|M_k|^2, 3D ones do not");
 
 template <class St> struct StepArgs {
     const typename St::TF* fsrc;
@@ -388,7 +396,10 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
             const R mk = flow_moment(kc);
             d = -c.s[kind] * (mk - eq_dev<DIM>(k, rho, drho, u)) + c.b[kind] * force_mom<DIM>(k, u, F);
         }
-        dm[k] = d * R(1.0 / row_norm<L>(k));
+        // the rates of non-conserved rows already carry 1/|M_k|^2 when folded
+        constexpr bool scaled = folded_rates<DIM>() && kind != kRho && kind != kJx && kind != kJy && kind != kJz;
+        if constexpr (scaled) dm[k] = d;
+        else dm[k] = d * R(1.0 / row_norm<L>(k));
     });
     {
         R acc = hf[0];
@@ -426,7 +437,8 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
             else if constexpr (kind == kE) d = -c.q[kind] * (nk - c.a_t * dT);
             else d = -c.q[kind] * nk;
         }
-        dn[k] = d * R(1.0 / row_norm<H>(k));
+        if constexpr (folded_rates<DIM>()) dn[k] = d;  // q carries 1/|N_k|^2 (d = 0 on row 0)
+        else dn[k] = d * R(1.0 / row_norm<H>(k));
     });
     {
         R acc = hg[0];
@@ -667,15 +679,17 @@ __device__ __forceinline__ int32_t region_coord(int32_t v, uint32_t n, int32_t p
 // each step reads the rows of the step before it from earlier iterations.
 template <int NS> constexpr int strip_cols() { return 64 - 2 * NS; }
 
-// the value of v held by lane l - 1 (FromLeft) or lane l + 1 (otherwise)
+// the value of v held by lane l - 1 (FromLeft) or lane l + 1 (otherwise);
+// lane 0 (63) has no source and reads 0 (bound_ctrl), so no old value has
+// to be set up first
 template <bool FromLeft> __device__ __forceinline__ float lane_shift(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                  FromLeft ? 0x138 : 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v),
+                                                               FromLeft ? 0x138 : 0x130, 0xf, 0xf, true));
 }
 template <bool FromLeft> __device__ __forceinline__ double lane_shift(double v) {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, FromLeft ? 0x138 : 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), FromLeft ? 0x138 : 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, FromLeft ? 0x138 : 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), FromLeft ? 0x138 : 0x130, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 

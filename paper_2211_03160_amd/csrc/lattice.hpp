@@ -147,4 +147,25 @@ template <class L> constexpr int row_norm(int k) {
     return acc;
 }
 
+// |M_k|^2 shared by every row of one kind, or 0 if they differ
+template <class L> constexpr int kind_norm(int kind) {
+    int n = 0;
+    for (int k = 0; k < L::Q; ++k) {
+        if (L::kind[k] != kind) continue;
+        const int r = row_norm<L>(k);
+        if (n == 0) n = r;
+        else if (n != r) return 0;
+    }
+    return n;
+}
+
+// true when every kind's rows share |M_k|^2, so that a relaxation rate per
+// kind can carry the 1/|M_k|^2 of the inverse transform (D2Q9 and D2Q5: yes;
+// D3Q19, whose rows 3p_xx and p_ww relax together: no)
+template <class L> constexpr bool kinds_share_norm() {
+    for (int k = 0; k < L::Q; ++k)
+        if (kind_norm<L>(L::kind[k]) == 0) return false;
+    return true;
+}
+
 }  // namespace lbm

@@ -242,11 +242,15 @@ template <class R> Coef<R> make_coef(const lbm_ctx* c) {
         default: return 0.0;
         }
     };
+    // in 2D each kind's rate also carries 1/|M_k|^2 of its rows (folded_rates)
+    const bool fold = c->p.dim == 2;
     for (int kind = 0; kind < 10; ++kind) {
         const double s = flow_rate(kind);
-        k.s[kind] = (R)s;
-        k.b[kind] = (R)(1.0 - 0.5 * s);
-        k.q[kind] = (R)heat_rate(kind);
+        const int nf = fold ? kind_norm<Flow<2>>(kind) : 0, ng = fold ? kind_norm<Heat<2>>(kind) : 0;
+        const double sf = nf > 0 ? 1.0 / nf : 1.0, sg = ng > 0 ? 1.0 / ng : 1.0;
+        k.s[kind] = (R)(s * sf);
+        k.b[kind] = (R)((1.0 - 0.5 * s) * sf);
+        k.q[kind] = (R)(heat_rate(kind) * sg);
     }
     k.a_t = (R)v[LBM_D_A_T];
     k.gbeta = (R)v[LBM_D_GBETA];
