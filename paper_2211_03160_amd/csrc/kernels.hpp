@@ -726,6 +726,14 @@ template <class St, int QF, int QG> struct RegDst {
     __device__ void sg(int i, typename St::TG v) const { g[i] = St::EG::dec(v); }
 };
 
+// the encoded values of a node's update, kept for stores issued later
+template <class St, int QF, int QG> struct EncDst {
+    typename St::TF (&f)[QF];
+    typename St::TG (&g)[QG];
+    __device__ void sf(int i, typename St::TF v) const { f[i] = v; }
+    __device__ void sg(int i, typename St::TG v) const { g[i] = v; }
+};
+
 // Global stores for the lanes that own their node.  Stores and loads
 // retire through one in-order counter, and a store under a branch leaves
 // the compiler unsure it was issued, so it then waits for more of the
@@ -842,12 +850,13 @@ void stream_kernel(StreamArgs<St> a) {
     // the compiler drains every outstanding load before the next row.)
     const int32_t last = (int32_t)g.ny - 1;
     const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
-    // Row y of step j < NS feeds a stored result only inside the dependency
-    // cone of the segment, rows y0 - (NS - j) .. y0 + rows - 1 + (NS - j);
-    // elsewhere (while the step pipeline fills and drains) the step is
-    // skipped by a wavefront-uniform branch, and nothing needed reads the
-    // ring slot it would have written.  Step NS always runs: a branch around
-    // its stores would make the compiler wait for them before later loads.
+    // Row y of step j feeds a stored result only inside the dependency cone
+    // of the segment, rows y0 - (NS - j) .. y0 + rows - 1 + (NS - j) (for
+    // j = NS the segment itself); elsewhere (while the step pipeline fills
+    // and drains) the update is skipped by a wavefront-uniform branch, and
+    // nothing needed reads the ring slot it would have written.  The stores
+    // of step NS stay outside any branch: a branch around them would make
+    // the compiler wait for them before later loads.
     // (FP64 arithmetic keeps every step: the branches cost it registers.)
     auto needed = [&](int j, int32_t y) {
         const int32_t rel = y - y0;
@@ -860,10 +869,14 @@ void stream_kernel(StreamArgs<St> a) {
         constexpr auto in = [](int j) { return ((S - j) % NI + NI) % NI; };
         constexpr auto st = [](int j) { return ((S - j) % RS + RS) % RS; };
         const int32_t yin = y0 - NS + k;
-        // 1. issue the loads of input row yin (its slot held row yin - NI)
+        // 1. issue the loads of input row yin (its slot held row yin - NI).
+        //    Past the last row the segment needs (y0 + rows - 1 + NS, while
+        //    the pipeline drains) the loads repeat that row, which the cache
+        //    still holds: what they feed is never stored.
         {
-            const int32_t rin = region_coord(yin, g.ny, g.periodic[1]);
-            const uint32_t row_in = (uint32_t)(rin >= 0 ? rin : min(max(yin, 0), last));
+            const int32_t yl = min(yin, y0 + rows - 1 + NS);
+            const int32_t rin = region_coord(yl, g.ny, g.periodic[1]);
+            const uint32_t row_in = (uint32_t)(rin >= 0 ? rin : min(max(yl, 0), last));
             const uint32_t node = ucol + g.nx * row_in;
             const uint32_t bf = pop_at<QF>(node, 0), bg = pop_at<QG>(node, 0);
             static_for<0, QF>([&](auto ic) {
@@ -891,8 +904,20 @@ void stream_kernel(StreamArgs<St> a) {
             const PtrFlux2 fx{a.flux, a.slot[(a.t_parity + j) & 1], own};
             if constexpr (j == NS) {
                 if constexpr (O32) {
+                    // The update runs only on the segment's rows (needed(NS, y)
+                    // is exactly them); the stores always issue, from zeros
+                    // and to the dropped offset elsewhere.
+                    typename St::TF ef[QF];
+                    typename St::TG eg[QG];
+                    if (needed(NS, yj)) {
+                        step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, EncDst<St, QF, QG>{ef, eg}, fx);
+                    } else {
+                        static_for<0, QF>([&](auto ic) { ef[decltype(ic)::value] = typename St::TF{}; });
+                        static_for<0, QG>([&](auto ic) { eg[decltype(ic)::value] = typename St::TG{}; });
+                    }
                     const OwnedBufDst<St, QF, QG> dst(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, own);
-                    step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                    static_for<0, QF>([&](auto ic) { dst.sf(decltype(ic)::value, ef[decltype(ic)::value]); });
+                    static_for<0, QG>([&](auto ic) { dst.sg(decltype(ic)::value, eg[decltype(ic)::value]); });
                 } else {
                     const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, own);
                     step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);

@@ -409,8 +409,9 @@ namespace {
 
 // Steps per launch a 2D context starts with: the fastest measured on the
 // 8193^2 cell per storage mode (GLUPS at 1/2/3/4 steps, each with its best
-// segment length: FP32 51/69/113/137, FP16-f+FP32-g 74/98/146/155, FP16
-// 103/125/152/153, BF16 99/119/136/110, FP64 25/38/30/-).
+// segment length, before the pipeline fill was skipped: FP32 51/69/113/137,
+// FP16-f+FP32-g 74/98/146/155, FP16 103/125/152/153, BF16 99/119/136/110,
+// FP64 25/38/30/-).
 int32_t default_steps_per_launch(int32_t storage) {
     switch (storage) {
     case LBM_FP32: return 4;
@@ -437,22 +438,23 @@ bool fits_o32(const lbm_ctx* c) {
 // k launches of the register-row kernel of NS steps each (prefetch distance
 // D rows), A -> B, advancing t by NS k
 // Rows per strip segment (one wavefront each), by storage and steps per
-// launch, measured on the 8193^2 cell.  Launches that move many bytes per
-// update run fastest with short segments, even though the first and last
-// rows of every segment repeat part of the dependency cone (FP32 at three
-// steps: 115 / 104 / 96 GLUPS at 16 / 32 / 64 rows; FP64 at two: 38 / 35 /
-// 35); FP32 at four steps peaks at 24 (134 / 139 / 137 / 124 at 16 / 24 /
-// 32 / 64), FP16-f+FP32-g at four near 64-80 (139 / 151 / 152 / 155 / 146
-// at 24 / 48 / 64 / 80 / 128) and FP16 / BF16 at three near 40-64 (FP16
-// 141 / 155 / 154 at 16 / 40 / 64, BF16 122 / 138 / 140).
+// launch, measured on the 8193^2 cell.  Every segment repeats the rows of
+// its dependency cone outside it and runs its last step over the pipeline
+// fill, so longer segments waste less arithmetic; launches that move many
+// bytes per update still run fastest with short ones (FP32 at three steps:
+// 117 / 111 / 107 / 97 GLUPS at 16 / 24 / 32 / 64 rows; FP64 at two: 39 /
+// 37 / 36 / 36).  FP32 at four steps: 147 / 147 / 143 / 128 at 16 / 24 /
+// 32 / 64; FP16-f+FP32-g at four: 150 / 165 / 171 / 171 at 16 / 32 / 48 /
+// 64; FP16 at three: 162 / 168 / 164 / 161 at 16 / 32 / 48 / 64, BF16 at
+// three 139 / 147 / 149 / 148.
 template <class St, int NS> constexpr uint32_t stream_seg_rows() {
     constexpr bool f32 = sizeof(typename St::TF) == 4 && sizeof(typename St::TG) == 4;
     constexpr bool f64 = sizeof(typename St::TF) == 8;
     constexpr bool half = sizeof(typename St::TF) == 2 && sizeof(typename St::TG) == 2;
     if constexpr (f64) return NS == 2 ? 16 : 64;
     else if constexpr (f32) return NS == 4 ? 24 : 16;
-    else if constexpr (half) return NS == 2 ? 40 : NS == 3 ? 48 : 64;
-    else return NS == 2 ? 16 : NS == 3 ? 40 : 64;  // FP16 f, FP32 g
+    else if constexpr (half) return NS == 2 ? 40 : NS == 3 ? 32 : 64;
+    else return NS == 2 ? 16 : NS == 3 ? 40 : 48;  // FP16 f, FP32 g
 }
 
 template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
