@@ -77,6 +77,25 @@ def read_traffic(steps_per_launch):
         return None
 
 
+def read_valu_instructions():
+    """VALU wave instructions per launch of the four-step FP32 kernel from
+    the committed rocprofv3 run, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "valu_d2q9_fp32_8193.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_hash():
+        return None
+    try:
+        return float(kv["stream_valu_instructions_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def timed_steps(cav, steps):
     """Average wall time per step over `steps` launches, measured with HIP
     events recorded on the stream the kernels are launched on."""
@@ -139,18 +158,25 @@ def batched_sweep(K, warmup, noise):
     flagged = int(b.unstable().sum())
     del b
     torch.cuda.empty_cache()
-    ms_seq = 0.0
+    # the same cavities one after another: with one step per launch (the
+    # batch's own per-step kernel) and in each cavity's default launch mode
+    ms_seq = {1: 0.0, 0: 0.0}
     for c, sd in zip(cfgs, seeds):
-        cav = lbm.Cavity(c)
-        cav.init(sd, noise)
-        cav.step(5)
-        ms_seq += timed_steps(cav, K) * K
-        del cav
+        for spl in ms_seq:
+            cav = lbm.Cavity(c)
+            if spl:
+                cav.steps_per_launch = spl
+            cav.init(sd, noise)
+            cav.step(8)
+            ms_seq[spl] += timed_steps(cav, K) * K
+            del cav
     torch.cuda.empty_cache()
     return {"cavities": len(cfgs), "nodes": nodes, "steps": K,
             "glups": nodes * K / (ms_batch * 1e-3) / 1e9,
-            "glups_sequential": nodes * K / (ms_seq * 1e-3) / 1e9,
-            "speedup_vs_sequential": ms_seq / ms_batch,
+            "glups_sequential_one_step_per_launch": nodes * K / (ms_seq[1] * 1e-3) / 1e9,
+            "speedup_vs_sequential_one_step_per_launch": ms_seq[1] / ms_batch,
+            "glups_sequential_default_launch": nodes * K / (ms_seq[0] * 1e-3) / 1e9,
+            "speedup_vs_sequential_default_launch": ms_seq[0] / ms_batch,
             "ms_per_step": ms_batch / K, "config": {**best, "graph_steps": graph_steps},
             "tuner_ms_per_step": [round(m, 4) for m in cand_ms],
             "unstable_cavities": flagged}
@@ -323,11 +349,16 @@ def main():
     traffic = read_traffic(spl)
     if spl > 1:
         tflops = head["glups"] * FLOPS_PER_UPDATE_2D / 1e3
+        # VALU issue slots the launch uses: instructions x 4 cycles per
+        # SIMD over 1024 SIMDs at 2.4 GHz, during the HIP-event launch time
+        insts = read_valu_instructions() if spl == 4 else None
+        valu_issue = round(insts * 4 / 1024 / 2.4e9 / launch_s, 4) if insts else None
         roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                     "kernel": f"lbm::stream_kernel<StF32, 4, true, {spl}, 0>",
                     "flops_per_lattice_update": FLOPS_PER_UPDATE_2D,
                     "frac_of_packed_fp32_peak": round(tflops / PEAK_FP32_PACKED_TFLOPS, 4),
+                    "valu_issue_frac": valu_issue,
                     "hbm_algorithmic_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / PEAK_HBM_GBS, 4)}
     else:
         roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": PEAK_HBM_GBS,
