@@ -180,7 +180,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n);
  * results are bitwise identical; only the global memory traffic per step
  * drops to 1/k.  A count of steps that k does not divide ends with shorter
  * launches.  LBM_E_INVALID for other values, LBM_E_UNSUPPORTED for k > 1
- * in 3D, LBM_E_STATE for a batch member.                               */
+ * in 3D and for k > 2 with FP64 storage (its deeper register rings do not
+ * fit), LBM_E_STATE for a batch member.                                 */
 lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps);
 int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
 
@@ -236,12 +237,14 @@ const char* lbm_version(void);
 
 /* ------------------------------------------------------------- batches
  * Many independent cavities of different sizes and parameters (same dim
- * and storage) advanced together: every lbm_batch_step launch updates all
- * nodes of all cavities with the per-node arithmetic of lbm_step, so each
- * cavity evolves exactly as it would alone (the physics is Section 2.2's,
- * per cavity; batching is a launch strategy).  All cavities share the time
- * step counter.  The batch workspace holds every cavity's state plus the
- * work tables; the library never allocates device memory.               */
+ * and storage) advanced together: every launch of lbm_batch_step updates
+ * all nodes of all cavities, by 2-4 steps in 2D (the streaming kernel of
+ * lbm_set_steps_per_launch, over the work units of every cavity) or by one,
+ * with the per-node arithmetic of lbm_step, so each cavity evolves exactly
+ * as it would alone (the physics is Section 2.2's, per cavity; batching is
+ * a launch strategy).  All cavities share the time step counter.  The batch
+ * workspace holds every cavity's state plus the work tables; the library
+ * never allocates device memory.                                        */
 typedef struct lbm_batch lbm_batch;
 
 typedef struct lbm_batch_config {
@@ -249,9 +252,10 @@ typedef struct lbm_batch_config {
     int32_t grid_per_cu; /* 0: one block per work unit of `block` nodes;
                             k > 0: persistent grid of k blocks per compute
                             unit, looping over the units                      */
-    int32_t graph_steps; /* 0: launch every step; G > 0 (even): capture G
-                            steps once into a hipGraph and replay it (needs a
-                            non-default stream; ignored on the NULL stream)  */
+    int32_t graph_steps; /* 0: launch every time; G > 0 (even): capture the
+                            launches of G steps once into a hipGraph and
+                            replay it (needs a non-default stream; ignored on
+                            the NULL stream)                                  */
     int32_t reserved;    /* 0                                                 */
 } lbm_batch_config;
 
@@ -274,8 +278,20 @@ lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t k, const double* rho, con
                                  const double* T);
 
 /* Enqueues n steps of every cavity (graph replays when configured, then
- * single launches for the remainder).  Asynchronous.                    */
+ * launches of lbm_batch_get_steps_per_launch steps, then one-step launches
+ * for the remainder).  Asynchronous.                                    */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Steps per launch of lbm_batch_step: 1 (batch_step_kernel, the shape of
+ * lbm_batch_config) or 2..4 (the streaming kernel; 2D batches whose
+ * cavities' population arrays are each under 4 GiB).  A batch starts with
+ * the count a single cavity of its storage mode starts with, where
+ * streaming is available, else 1.  Results do not depend on it (bitwise).
+ * LBM_E_INVALID outside 1..4, LBM_E_UNSUPPORTED for k > 1 where streaming
+ * is not available and for k > 2 with FP64 storage.  Synchronises the
+ * batch stream when the count changes (the work tables are rewritten).  */
+lbm_status lbm_batch_set_steps_per_launch(lbm_batch* b, int32_t steps);
+int32_t lbm_batch_get_steps_per_launch(const lbm_batch* b); /* 0 for NULL */
 
 /* Borrowed view of cavity k, owned by the batch: lbm_fields, lbm_nusselt,
  * lbm_wall_flux, lbm_diagnostics and lbm_export_state work on it;
@@ -292,10 +308,11 @@ lbm_status lbm_batch_nusselt(lbm_batch* b, double* nu_hot, double* nu_cold);
  * (its divergence does not affect the other cavities).  Synchronises.   */
 lbm_status lbm_batch_unstable(lbm_batch* b, int32_t* flags);
 
-/* Autotuner: times `steps` launches of each candidate launch shape (block
- * 128/256/512 x grid_per_cu 0/2/4/8) with HIP events on the batch stream
- * and keeps the fastest (graph_steps is left as configured).  The timing
- * steps are real steps: t advances by 12 (steps + 1).  ms_per_step
+/* Autotuner of the one-step kernel: times `steps` one-step launches of
+ * each candidate launch shape (block 128/256/512 x grid_per_cu 0/2/4/8)
+ * with HIP events on the batch stream and keeps the fastest (graph_steps
+ * is left as configured; the streaming kernel's shape is fixed).  The
+ * timing steps are real steps: t advances by 12 (steps + 1).  ms_per_step
  * (nullable) receives up to 12 timings, ncand their number.            */
 lbm_status lbm_batch_tune(lbm_batch* b, int32_t steps, lbm_batch_config* best, double* ms_per_step,
                           int32_t* ncand);

@@ -814,18 +814,19 @@ template <class St, int NS> constexpr int stream_waves_per_simd() {
     else return LBM_STREAM_WAVES_PER_SIMD;
 }
 
-template <class St, int NWB, bool O32, int NS, int D>
-__global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St, NS>())))
-void stream_kernel(StreamArgs<St> a) {
+// One wavefront's work unit (strip unit % strips, row segment unit /
+// strips) of a, advancing NS steps from the state of parity tp.  With
+// Report, returns false on a lane that owns a node whose new rho or T is not
+// finite.
+template <class St, bool O32, int NS, int D, bool Report>
+__device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t unit, int32_t tp) {
     using R = typename St::R;
     constexpr int QF = Flow<2>::Q, QG = Heat<2>::Q;
     constexpr int W = strip_cols<NS>();
     static_assert(NS >= 2 && NS <= 4, "two to four steps per launch");
     const Geometry& g = a.geo;
     const int lane = (int)(threadIdx.x & 63);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t unit = logical_block(a.blocks_per_xcd) * NWB + wave;
-    if (unit >= a.units) return;  // whole wavefront
+    bool bad = false;
     const int32_t x0 = (int32_t)((unit % a.strips) * W);
     const int32_t y0 = (int32_t)((unit / a.strips) * a.seg_rows);
     const int32_t rows = min((int32_t)a.seg_rows, (int32_t)g.ny - y0);
@@ -901,7 +902,7 @@ void stream_kernel(StreamArgs<St> a) {
             const Neighbours nb = neighbours(g, x, yy, 0);
             const RegSrc<St, QF, QG> src{fs[j - 2][st(3)], fs[j - 2][st(2)], fs[j - 2][st(1)],
                                          gs[j - 2][st(3)], gs[j - 2][st(2)], gs[j - 2][st(1)]};
-            const PtrFlux2 fx{a.flux, a.slot[(a.t_parity + j) & 1], own};
+            const PtrFlux2 fx{a.flux, a.slot[(tp + j) & 1], own};
             if constexpr (j == NS) {
                 if constexpr (O32) {
                     // The update runs only on the segment's rows (needed(NS, y)
@@ -910,7 +911,8 @@ void stream_kernel(StreamArgs<St> a) {
                     typename St::TF ef[QF];
                     typename St::TG eg[QG];
                     if (needed(NS, yj)) {
-                        step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, EncDst<St, QF, QG>{ef, eg}, fx);
+                        const bool ok = step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, EncDst<St, QF, QG>{ef, eg}, fx);
+                        if constexpr (Report) bad = bad || (own && !ok);
                     } else {
                         static_for<0, QF>([&](auto ic) { ef[decltype(ic)::value] = typename St::TF{}; });
                         static_for<0, QG>([&](auto ic) { eg[decltype(ic)::value] = typename St::TG{}; });
@@ -920,7 +922,8 @@ void stream_kernel(StreamArgs<St> a) {
                     static_for<0, QG>([&](auto ic) { dst.sg(decltype(ic)::value, eg[decltype(ic)::value]); });
                 } else {
                     const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, own);
-                    step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                    const bool ok = step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                    if constexpr (Report) bad = bad || (own && !ok);
                 }
             } else if (needed(j, yj)) {
                 const RegDst<St, QF, QG> dst{fs[j - 1][st(0)], gs[j - 1][st(0)]};
@@ -938,7 +941,7 @@ void stream_kernel(StreamArgs<St> a) {
             const RegDst<St, QF, QG> dst{fs[0][st(0)], gs[0][st(0)]};
             const bool own = own_col && y1 >= y0 && y1 < y0 + rows;
             step_node<2, St, Wl>(g, a.c, nb, ucol, yy, 0u, src, dst,
-                                 PtrFlux2{a.flux, a.slot[(a.t_parity + 1) & 1], own});
+                                 PtrFlux2{a.flux, a.slot[(tp + 1) & 1], own});
         }
     };
     // step NS reaches row y0 + rows - 1 at k = rows + 3 NS - 2 + D; the
@@ -959,6 +962,40 @@ void stream_kernel(StreamArgs<St> a) {
         sweep(std::false_type{});
     else
         sweep(std::true_type{});
+    return !bad;
+}
+
+template <class St, int NWB, bool O32, int NS, int D>
+__global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St, NS>())))
+void stream_kernel(StreamArgs<St> a) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t unit = logical_block(a.blocks_per_xcd) * NWB + wave;
+    if (unit >= a.units) return;  // whole wavefront
+    stream_unit<St, O32, NS, D, false>(a, unit, a.t_parity);
+}
+
+// Many 2D cavities, several steps per launch: wavefront w takes work unit w
+// of the concatenated units of all cavities; unit_cavity maps it to its
+// cavity, whose arguments (for either source buffer) sit in desc.
+template <class St> struct BatchStreamArgs {
+    const StreamArgs<St>* desc;   // [2][count]: the cavities' arguments with buffer A, B as source
+    const uint16_t* unit_cavity;  // [units]
+    const uint32_t* unit0;        // [count] first unit of each cavity
+    uint32_t units, count, blocks_per_xcd;
+    int32_t src;                  // source buffer of this launch
+    int32_t t_parity;             // (t of the input state) mod 2
+    int32_t* unstable;            // per-cavity flag, set on a non-finite node
+};
+
+template <class St, int NWB, bool O32, int NS, int D>
+__global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St, NS>())))
+void batch_stream_kernel(BatchStreamArgs<St> b) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t unit = logical_block(b.blocks_per_xcd) * NWB + wave;
+    if (unit >= b.units) return;  // whole wavefront
+    const uint32_t k = b.unit_cavity[unit];
+    const StreamArgs<St>& a = b.desc[(uint32_t)b.src * b.count + k];
+    if (!stream_unit<St, O32, NS, D, true>(a, unit - b.unit0[k], b.t_parity)) b.unstable[k] = 1;
 }
 
 // --------------------------------------------------------- batched cavities
@@ -1239,21 +1276,23 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(double* p, size_t n, doubl
         p[i] = v;
 }
 
-// per-cavity wall heat flux sums: block (k, b) reduces buffer b of cavity k
+// per-cavity wall heat flux sums: block (k, b) reduces buffer b of cavity k,
+// in the order of face_sum_kernel, so that a batch member's sums equal those
+// of the same cavity run alone bit for bit
 struct BatchFaceArgs {
     const double* const* buf;  // [count][12]
     const uint32_t* len;       // [count][12]
     double* out;               // [count][12]
 };
 
-__global__ __launch_bounds__(256) void batch_face_sum_kernel(BatchFaceArgs a) {
-    __shared__ double lds[256 / 64];
+__global__ __launch_bounds__(1024) void batch_face_sum_kernel(BatchFaceArgs a) {
+    __shared__ double lds[1024 / 64];
     const size_t b = blockIdx.x;
     const double* p = a.buf[b];
     double acc = 0.0;
     if (p)
-        for (uint32_t i = threadIdx.x; i < a.len[b]; i += 256) acc += p[i];
-    const double r = block_reduce<256>(acc, AddOp{}, lds);
+        for (uint32_t i = threadIdx.x; i < a.len[b]; i += 1024) acc += p[i];
+    const double r = block_reduce<1024>(acc, AddOp{}, lds);
     if (threadIdx.x == 0) a.out[b] = r;
 }
 

@@ -412,6 +412,13 @@ namespace {
 // segment length, before the pipeline fill was skipped: FP32 51/69/113/137,
 // FP16-f+FP32-g 74/98/146/155, FP16 103/125/152/153, BF16 99/119/136/110,
 // FP64 25/38/30/-).
+// FP64 streams at most two steps per launch: the rings of deeper launches
+// (two registers per value) do not fit the 256 registers, the kernels spill
+// heavily and run slower (28 and 18 GLUPS at three and four steps, against
+// 39 at two), and at four steps on arrays over 4 GiB the results differed
+// from single steps on the columns next to strip edges.
+constexpr int kMaxStepsFp64 = 2;
+
 int32_t default_steps_per_launch(int32_t storage) {
     switch (storage) {
     case LBM_FP32: return 4;
@@ -663,13 +670,16 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         constexpr int DIM = decltype(dimc)::value;
         using St = decltype(stc);
         if constexpr (DIM == 2) {
-            if (c->steps_per_launch == 4 && n >= 4) {
-                stream_launches<St, 4, 0>(c, n / 4);
-                n -= n / 4 * 4;
-            }
-            if (c->steps_per_launch >= 3 && n >= 3) {
-                stream_launches<St, 3, 0>(c, n / 3);
-                n -= n / 3 * 3;
+            constexpr bool deep = sizeof(typename St::R) == 4;  // FP64: at most two (kMaxStepsFp64)
+            if constexpr (deep) {
+                if (c->steps_per_launch == 4 && n >= 4) {
+                    stream_launches<St, 4, 0>(c, n / 4);
+                    n -= n / 4 * 4;
+                }
+                if (c->steps_per_launch >= 3 && n >= 3) {
+                    stream_launches<St, 3, 0>(c, n / 3);
+                    n -= n / 3 * 3;
+                }
             }
             if (c->steps_per_launch >= 2 && n >= 2) {
                 stream_launches<St, 2, LBM_STREAM_AHEAD>(c, n / 2);
@@ -704,6 +714,8 @@ lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps) {
     if (steps < 1 || steps > 4) return set_err(c->err, LBM_E_INVALID, "steps per launch must lie in 1 .. 4");
     if (steps > 1 && c->p.dim != 2)
         return set_err(c->err, LBM_E_UNSUPPORTED, "several steps per launch are implemented in 2D only");
+    if (steps > kMaxStepsFp64 && c->p.storage == LBM_FP64)
+        return set_err(c->err, LBM_E_UNSUPPORTED, "FP64 runs at most %d steps per launch", kMaxStepsFp64);
     c->steps_per_launch = steps;
     return LBM_OK;
 }

@@ -34,6 +34,7 @@ EXPORTS = ["lbm_derive", "lbm_workspace_bytes", "lbm_bytes_per_update",
            "lbm_batch_init", "lbm_batch_init_fields", "lbm_batch_step",
            "lbm_batch_cavity", "lbm_batch_nusselt", "lbm_batch_unstable",
            "lbm_batch_tune", "lbm_batch_set_config", "lbm_batch_get_config",
+           "lbm_batch_set_steps_per_launch", "lbm_batch_get_steps_per_launch",
            "lbm_batch_time", "lbm_batch_destroy", "lbm_batch_last_error"]
 
 
@@ -129,6 +130,9 @@ def lib():
         L.lbm_batch_tune.argtypes = [P, C.c_int32, bp, dp, C.POINTER(C.c_int32)]
         L.lbm_batch_set_config.argtypes = [P, bp]
         L.lbm_batch_get_config.argtypes = [P, bp]
+        L.lbm_batch_set_steps_per_launch.argtypes = [P, C.c_int32]
+        L.lbm_batch_get_steps_per_launch.argtypes = [P]
+        L.lbm_batch_get_steps_per_launch.restype = C.c_int32
         L.lbm_batch_time.argtypes = [P]
         L.lbm_batch_time.restype = C.c_int64
         L.lbm_batch_destroy.argtypes = [P]
@@ -138,7 +142,7 @@ def lib():
         for name in ("lbm_batch_create", "lbm_batch_init", "lbm_batch_init_fields",
                      "lbm_batch_step", "lbm_batch_cavity", "lbm_batch_nusselt",
                      "lbm_batch_unstable", "lbm_batch_tune", "lbm_batch_set_config",
-                     "lbm_batch_get_config"):
+                     "lbm_batch_get_config", "lbm_batch_set_steps_per_launch"):
             getattr(L, name).restype = C.c_int32
         for name in ("lbm_derive", "lbm_create", "lbm_init", "lbm_init_fields",
                      "lbm_step", "lbm_set_steps_per_launch", "lbm_fields",
@@ -413,6 +417,15 @@ class Batch:
     @property
     def t(self) -> int:
         return int(lib().lbm_batch_time(self._h))
+
+    @property
+    def steps_per_launch(self) -> int:
+        """Steps per launch of step(): 1, or 2..4 (streaming, 2D)."""
+        return int(lib().lbm_batch_get_steps_per_launch(self._h))
+
+    @steps_per_launch.setter
+    def steps_per_launch(self, k: int):
+        self._check(lib().lbm_batch_set_steps_per_launch(self._h, int(k)))
 
     def cavity(self, k: int) -> Cavity:
         h = C.c_void_p()

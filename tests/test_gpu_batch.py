@@ -1,8 +1,8 @@
 """GPU tests of the batched launch (lbm_batch_*): every cavity of a batch
 must evolve exactly as the same cavity run alone (the per-node arithmetic is
-shared), under every launch shape, with and without hipGraph replay, and a
-diverging cavity must not disturb the others.  One FP64 batch member is also
-compared with the CPU oracle."""
+shared), with one or several steps per launch, under every launch shape,
+with and without hipGraph replay, and a diverging cavity must not disturb
+the others.  One FP64 batch member is also compared with the CPU oracle."""
 import numpy as np
 import pytest
 
@@ -214,3 +214,79 @@ def test_sweep_recipe_runs_and_tunes():
     ok = ~flags
     assert np.all(np.isfinite(hot[ok])) and np.all(np.isfinite(cold[ok]))
     print("sweep tune", best, ms, "flagged", int(flags.sum()), flush=True)
+
+
+def test_batch_steps_per_launch_defaults_and_arguments():
+    """2D batches start streaming with a single cavity's default count; 3D
+    ones with one step per launch and refuse more."""
+    for storage, k in (("fp32", 4), ("mixed", 4), ("fp16", 3), ("bf16", 3), ("fp64", 2)):
+        assert lbm.Batch(_small_batch(storage, 2)).steps_per_launch == k, storage
+    b = lbm.Batch(_small_batch("fp32", 2))
+    for bad in (0, 5, -1):
+        with pytest.raises(lbm.LBMError) as e:
+            b.steps_per_launch = bad
+        assert e.value.status == -1
+    for k in (1, 2, 3, 4):
+        b.steps_per_launch = k
+        assert b.steps_per_launch == k
+    b64 = lbm.Batch(_small_batch("fp64", 2))
+    with pytest.raises(lbm.LBMError) as e:
+        b64.steps_per_launch = 3
+    assert e.value.status == -5
+    b3 = lbm.Batch(_small_batch("fp32", 3))
+    assert b3.steps_per_launch == 1
+    with pytest.raises(lbm.LBMError) as e:
+        b3.steps_per_launch = 2
+    assert e.value.status == -5
+
+
+@pytest.mark.parametrize("storage,spl", [(s, k) for s in ("fp32", "mixed", "fp16", "bf16") for k in (1, 2, 3, 4)]
+                         + [("fp64", 1), ("fp64", 2)])
+def test_streaming_batch_members_equal_single_runs(storage, spl):
+    """23 steps (launches of spl steps and single steps for the rest, spl
+    changed once mid-run): every member equals its single-cavity run bit
+    for bit, Nusselt numbers included."""
+    cfgs = _small_batch(storage, 2)
+    seeds = [5 + k for k in range(len(cfgs))]
+    amps = [1e-2] * len(cfgs)
+    ref = _singles(cfgs, seeds, amps, 23)
+    b = lbm.Batch(cfgs)
+    b.steps_per_launch = spl
+    b.init(seeds, amps)
+    b.step(10)
+    b.steps_per_launch = {1: 4, 2: 3, 3: 4, 4: 3}[spl] if storage != "fp64" else 3 - spl
+    b.step(13)
+    assert b.t == 23
+    hot, cold = b.nusselt()
+    for k in range(len(cfgs)):
+        assert _fields_equal(b.cavity(k).fields(), ref[k][0]), k
+        if ref[k][1] is not None:
+            assert (hot[k], cold[k]) == ref[k][1], k
+    assert not b.unstable().any()
+
+
+@pytest.mark.parametrize("graph_steps", [4, 6])
+def test_streaming_graph_replay_matches_eager(graph_steps):
+    """Graphs of four-step launches plus single steps (6 = one launch of
+    four and two single steps, which leaves the buffers swapped), keyed by
+    the parity of t and the buffer; each replay checked against eager."""
+    import torch
+    cfgs = _small_batch("fp32", 2)
+    seeds = list(range(len(cfgs)))
+    amps = [1e-2] * len(cfgs)
+    eager = lbm.Batch(cfgs)
+    graph = lbm.Batch(cfgs)
+    assert eager.steps_per_launch == graph.steps_per_launch == 4
+    graph.set_config(block=256, grid_per_cu=0, graph_steps=graph_steps)
+    eager.init(seeds, amps)
+    graph.init(seeds, amps)
+    for rep, n in enumerate((graph_steps, 2 * graph_steps + 1, 3, graph_steps, graph_steps + 2)):
+        eager.step(n)
+        graph.step(n)
+        x = torch.randn(1024, device="cuda")
+        torch.cuda.synchronize()
+        assert float((x * 0).sum()) == 0.0
+        assert graph.t == eager.t
+        for k in range(len(cfgs)):
+            assert _fields_equal(graph.cavity(k).fields(), eager.cavity(k).fields()), (rep, k)
+        assert np.array_equal(np.nan_to_num(graph.nusselt()[0]), np.nan_to_num(eager.nusselt()[0]))
