@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=on: a multiply is fused with an add only inside one source
 # expression, never across statements, so the same update rounds the same
-# way wherever it is inlined (the single-step and the two-step kernels must
+# way wherever it is inlined (the single-step and the streaming kernels must
 # agree bit for bit).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wall", "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
