@@ -162,3 +162,24 @@ def test_kernel_basis_reproduces_paper_forcing_vectors(dim):
             else:
                 ref += coef * u[names.index(term[0])] * F[names.index(term[1].lower())]
         assert abs(mf[k] - ref) < 1e-17
+
+
+def test_bench_gpu_count_and_profile_summaries():
+    """bench.py refuses more than one GPU, and the committed rocprofv3
+    summaries it reports from parse into the fields of its JSON line (their
+    source hash either matches the kernels or they are ignored)."""
+    import subprocess
+    import sys
+    import bench
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+    for spl in (4, 1):
+        t = bench.read_traffic(spl)
+        assert t is None or 7.5e9 < t < 1.2e10, (spl, t)
+    v = bench.read_valu_instructions()
+    assert v is None or 5e8 < v < 2e9
+    for name in ("stream4_d2q9_fp32_8193_counters.txt", "step_d2q9_fp32_8193_counters.txt",
+                 "valu_d2q9_fp32_8193.md", "memreq_d2q9_fp32_8193.md", "rb2d_8193_kernel_trace.md"):
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+        assert "rocprofv3" in text and "$REPO" in text, name
