@@ -72,11 +72,9 @@ struct E16 {
 struct EB16 {  // bfloat16 kept as raw bits
     using T = uint16_t;
     __device__ static float dec(T v) { return __uint_as_float((uint32_t)v << 16); }
-    __device__ static T enc(float v) {
-        const uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
-        return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-    }
+    // the hardware conversion (v_cvt_pk_bf16_f32): nearest even under the
+    // default rounding mode, FP32 denormals kept, NaN to a quiet NaN
+    __device__ static T enc(float v) { return __builtin_bit_cast(T, (__bf16)v); }
 };
 
 // A storage mode: codecs of f and g and the compute type R.
