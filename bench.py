@@ -206,9 +206,10 @@ def cpu_baseline(cfg2d, budget_s=12.0):
     from oracle.lbmref import Oracle, threads
     cfg = dict(cfg2d)
     cfg["n"] = (cfg2d["n"][0], 65, 1)
-    # keep the transport coefficients of the full cell
-    from paper_2211_03160_amd import lbm
-    d = lbm.derive(cfg2d)
+    # keep the transport coefficients of the full cell (the oracle's own
+    # parameter mapping)
+    from oracle.lbmref import derive
+    d = derive(cfg2d)
     cfg.update(nu=d["nu"], alpha=d["alpha"], gbeta=d["gbeta"])
     o = Oracle(cfg)
     o.init(1234, 1e-3)
@@ -266,7 +267,8 @@ def oracle_timing():
     timed("C0 129^2, 200 steps", c0, 0, 200, 1)
     strip = dict(W.C1["cfg"])
     strip["n"] = (8193, 65, 1)
-    d = __import__("paper_2211_03160_amd.lbm", fromlist=["derive"]).derive(W.C1["cfg"])
+    from oracle.lbmref import derive
+    d = derive(W.C1["cfg"])
     strip.update(nu=d["nu"], alpha=d["alpha"], gbeta=d["gbeta"], storage="fp64")
     timed("C1 strip 8193x65, 3 steps", strip, 1, 3, 1)
     timed("C1 8193^2 D2Q9+D2Q5, 3 steps", W.with_storage(W.C1["cfg"], "fp64"), 1, 3, all_threads)

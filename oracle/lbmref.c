@@ -452,6 +452,21 @@ int lbmref_create(const lbmref_params* p, lbmref_ctx** out) {
     return LBMREF_OK;
 }
 
+/* The parameter mapping of lbmref_create (Eqs. 2-4 in lattice units, the
+ * relaxation rates and the anti-bounce-back weight) without a state: no
+ * allocation.  out receives LBMREF_D_COUNT values.                      */
+int lbmref_derive(const lbmref_params* p, double* out) {
+    if (!p || !out) return fail(g_create_err, "null argument");
+    lbmref_ctx tmp;
+    memset(&tmp, 0, sizeof(tmp));
+    tmp.p = *p;
+    int st = derive(&tmp, g_create_err);
+    if (st) return st;
+    memcpy(out, tmp.d, sizeof(tmp.d));
+    g_create_err[0] = 0;
+    return LBMREF_OK;
+}
+
 void lbmref_destroy(lbmref_ctx* c) {
     if (!c) return;
     free(c->f); free(c->fp); free(c->g); free(c->gp);

@@ -61,7 +61,7 @@ typedef struct lbmref_diag {
     double mass;     /* sum of rho over all nodes                  */
     double energy;   /* sum of T over all nodes                    */
     double umax;     /* max |u|                                    */
-    double nu_vol;   /* 1 + L <u_g T> / (alpha dT)                 */
+    double nu_vol;   /* 1 + H <u_g (T - T0)> / (alpha dT)          */
     double re;       /* sqrt(<|u|^2>) H / nu                       */
     int64_t nonfinite;
 } lbmref_diag;
@@ -104,6 +104,9 @@ int lbmref_get_populations(const lbmref_ctx* c, double* f, double* g);
 int lbmref_set_populations(lbmref_ctx* c, const double* f, const double* g);
 
 int lbmref_derived(const lbmref_ctx* c, double* out /* LBMREF_D_COUNT */);
+/* the same values for parameters alone, without creating a state; errors
+ * as lbmref_create (message in lbmref_last_error(NULL))                 */
+int lbmref_derive(const lbmref_params* p, double* out /* LBMREF_D_COUNT */);
 
 /* lattice tables the oracle builds for `dim`, for the pin tests.
  * which: 0 = flow, 1 = thermal.  Outputs (each may be NULL):

@@ -75,6 +75,7 @@ def lib():
         L.lbmref_get_populations.argtypes = [P, dp, dp]
         L.lbmref_set_populations.argtypes = [P, dp, dp]
         L.lbmref_derived.argtypes = [P, dp]
+        L.lbmref_derive.argtypes = [C.POINTER(Params), dp]
         L.lbmref_lattice.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int),
                                      dp, dp, dp, dp]
         L.lbmref_splitmix64.argtypes = [C.c_uint64]
@@ -210,6 +211,17 @@ class Oracle:
         out = np.empty(len(DERIVED))
         self._check(lib().lbmref_derived(self._h, _dp(out)))
         return dict(zip(DERIVED, out.tolist()))
+
+
+def derive(cfg: dict) -> dict:
+    """The oracle's own parameter mapping for a run configuration (no state
+    is created)."""
+    p = make_params(cfg)
+    out = np.empty(len(DERIVED))
+    st = lib().lbmref_derive(C.byref(p), _dp(out))
+    if st != 0:
+        raise OracleError(st, lib().lbmref_last_error(None).decode())
+    return dict(zip(DERIVED, out.tolist()))
 
 
 def lattice(dim: int, thermal: bool):

@@ -57,11 +57,24 @@ MUTANTS = {
         "c->gaxis = p->dim == 2 ? 1 : 2;", "c->gaxis = p->dim == 2 ? 0 : 2;"),
     "Nusselt from one step only": (
         "double q = 0.5 * (c->flux[0][face] + c->flux[1][face]);", "double q = c->flux[c->t & 1][face];"),
+    "volume Nusselt number with T instead of T - T0": (
+        "uT += c->u[c->gaxis * N + idx] * (c->T[idx] - c->t0);", "uT += c->u[c->gaxis * N + idx] * c->T[idx];"),
+    "volume Nusselt number with the horizontal velocity": (
+        "uT += c->u[c->gaxis * N + idx] * (c->T[idx] - c->t0);", "uT += c->u[0 * N + idx] * (c->T[idx] - c->t0);"),
+    "volume Nusselt number with the viscosity": (
+        "d->nu_vol = 1.0 + c->H * (uT / N) / (c->alpha * c->dT);", "d->nu_vol = 1.0 + c->H * (uT / N) / (c->nu * c->dT);"),
+    "Reynolds number with the thermal diffusivity": (
+        "d->re = sqrt(u2 / N) * c->H / c->nu;", "d->re = sqrt(u2 / N) * c->H / c->alpha;"),
+    "Reynolds number without the square root": (
+        "d->re = sqrt(u2 / N) * c->H / c->nu;", "d->re = (u2 / N) * c->H / c->nu;"),
+    "Reynolds number with the width for H": (
+        "d->re = sqrt(u2 / N) * c->H / c->nu;", "d->re = sqrt(u2 / N) * c->n[0] / c->nu;"),
     "3D equilibrium basis row": (
         "case 10: return (3.0 * s - 5.0) * (3.0 * x * x - s);", "case 10: return (3.0 * s - 5.0) * (3.0 * y * y - s);"),
 }
 
-PINS = ["tests/test_oracle_lattice.py", "tests/test_oracle_collision.py", "tests/test_oracle_physics.py"]
+PINS = ["tests/test_oracle_lattice.py", "tests/test_oracle_collision.py", "tests/test_oracle_physics.py",
+        "tests/test_oracle_diagnostics.py"]
 
 
 def _run_mutant(name, tmp):
