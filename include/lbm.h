@@ -13,9 +13,11 @@
  *   - half-way bounce-back on no-slip walls, half-way anti-bounce-back on
  *     isothermal (Dirichlet) walls and bounce-back of g on adiabatic walls
  *     (Section 2.2), or periodic faces.
- * One time step is ONE fused GPU kernel: pull-streaming (Eqs. 8b, 9b) with
- * the wall rules, the moments, both collisions and the store of the
- * post-collision populations.
+ * Every time step is one fused pass: pull-streaming (Eqs. 8b, 9b) with the
+ * wall rules, the moments, both collisions and the store of the
+ * post-collision populations.  In 2D one kernel launch runs two to four
+ * such steps (lbm_set_steps_per_launch), keeping the intermediate rows in
+ * registers; in 3D one launch runs one step.
  *
  * Conventions
  *   - Every function returns an lbm_status (or a documented value); none
@@ -234,6 +236,22 @@ lbm_status lbm_lattice(int32_t dim, int32_t which, int32_t* q, int32_t* e,
 
 /* Host only.  Version string of the library build.                      */
 const char* lbm_version(void);
+
+/* HBM bandwidth probe: the ceiling a one-pass streaming kernel reaches on
+ * this GPU, against which the step kernels are measured (the step is
+ * bound by HBM bandwidth, Section 3.1).  One kernel launch on hip_stream
+ * (a hipStream_t, NULL = default stream), asynchronous:
+ *   kind 0: copy `bytes` from src to dst;
+ *   kind 1: read `bytes` of src (dst receives at most one 16-byte vector);
+ *   kind 2: write `bytes` of dst (src unused, may be NULL).
+ * per_thread: 16-byte vectors per thread, 1, 2, 4 or 8 (a block of 256
+ * threads moves 4 KiB x per_thread contiguous bytes); flags bit 0:
+ * non-temporal loads and stores.  src and dst are device pointers owned by
+ * the caller, 16-byte aligned, bytes a positive multiple of 16; the ranges
+ * must not overlap.  LBM_E_INVALID for other arguments, LBM_E_DEVICE if
+ * the launch fails.                                                      */
+lbm_status lbm_probe_bandwidth(int32_t kind, const void* src, void* dst, size_t bytes, int32_t per_thread,
+                               int32_t flags, void* hip_stream);
 
 /* ------------------------------------------------------------- batches
  * Many independent cavities of different sizes and parameters (same dim

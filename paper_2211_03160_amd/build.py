@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "liblbm.so")
-SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "nn_api.hip")]
+SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "nn_api.hip"), os.path.join(CSRC, "probe.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=on: a multiply is fused with an add only inside one source

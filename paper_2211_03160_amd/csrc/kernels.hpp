@@ -753,31 +753,23 @@ template <class St, int QF, int QG> struct OwnedBufDst {
     }
 };
 
-// the same for arrays of 4 GiB or more: branches around plain stores
-template <class St, int QF, int QG> struct OwnedGlobalDst : GlobalDst<St, QF, QG, false, false> {
-    bool own;
-    __device__ OwnedGlobalDst(typename St::TF* f_, typename St::TG* g_, uint32_t idx, bool own_)
-        : GlobalDst<St, QF, QG, false, false>(f_, g_, idx), own(own_) {}
-    __device__ void sf(int i, typename St::TF v) const {
-        if (own) GlobalDst<St, QF, QG, false, false>::sf(i, v);
-    }
-    __device__ void sg(int i, typename St::TG v) const {
-        if (own) GlobalDst<St, QF, QG, false, false>::sg(i, v);
-    }
-};
-
 // One flux slot in one array, the faces back to back (face f starts after
-// the node counts of faces 0 .. f-1; 2D).  Plain stores under a branch: only
-// lanes on a wall store, so the branch is almost never taken, and then the
-// compiler's assumption that the stores were not issued is exact (dropped-
-// lane buffer stores would cost a vector-memory issue slot each, every row).
-struct PtrFlux2 {
-    double* base;
-    uint32_t slot;
+// the node counts of faces 0 .. f-1; 2D).  Buffer stores like the
+// populations: a lane not on a Dirichlet wall link stores to the dropped
+// offset, so no code of the streaming kernels runs under a lane-divergent
+// branch.  (Under such a branch the register allocator may place the spill
+// of a value that every lane needs later, and a spill store executes for
+// the active lanes only: the other lanes would reload a stale value.)  The
+// stores are issued only by the sweep with wall rules, which runs on the
+// wavefronts next to a wall.
+struct BufFlux2 {
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t slot;   // first element of the slot
+    uint32_t bytes;  // size of the flux area: the dropped offset
     bool on;
     template <int face> __device__ void put(const Geometry& g, uint32_t local, double v, bool wall) const {
         const uint32_t start = face == 0 ? 0u : face == 1 ? g.ny : face == 2 ? 2u * g.ny : 2u * g.ny + g.nx;
-        if (on && wall) base[slot + start + local] = v;
+        buffer_store(v, r, on && wall ? (slot + start + local) * (uint32_t)sizeof(double) : bytes);
     }
 };
 
@@ -787,7 +779,8 @@ template <class St> struct StreamArgs {
     typename St::TF* fdst;
     typename St::TG* gdst;
     double* flux;                     // wall heat flux area: two slots, faces back to back
-    uint32_t f_bytes, g_bytes;        // sizes of fdst, gdst (buffer stores)
+    uint32_t flux_bytes;              // its size
+    uint32_t f_bytes, g_bytes;        // sizes of fdst, gdst (buffer stores; 0 for arrays of 4 GiB or more)
     uint32_t slot[2];                 // first element of flux slot 0 and slot 1
     int32_t t_parity;                 // (t of the input state) mod 2: step j writes slot (t + j) mod 2
     Geometry geo;
@@ -848,7 +841,25 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
     // loads would leave paths on which a load is not waited for, after which
     // the compiler drains every outstanding load before the next row.)
     const int32_t last = (int32_t)g.ny - 1;
-    const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
+    const __amdgpu_buffer_rsrc_t rflux = buffer_rsrc(a.flux, a.flux_bytes);
+    // Destinations of step NS in row yy: buffer resources over the whole
+    // arrays when byte offsets fit 32 bits (O32), else based at the first
+    // tile of the row (a wavefront-uniform base; a row and its halo span at
+    // most nx + 64 nodes), so both forms store without a branch.
+    auto row_dst = [&](uint32_t x, uint32_t yy, bool own) {
+        if constexpr (O32) {
+            return OwnedBufDst<St, QF, QG>(buffer_rsrc(a.fdst, a.f_bytes), buffer_rsrc(a.gdst, a.g_bytes),
+                                           a.f_bytes, a.g_bytes, x + g.nx * yy, own);
+        } else {
+            const uint32_t row0 = g.nx * yy;
+            const uint32_t t0 = row0 / kTile, tiles = (row0 + g.nx - 1) / kTile + 1 - t0;
+            const uint32_t fb = tiles * (uint32_t)(QF * kTile * sizeof(typename St::TF));
+            const uint32_t gb = tiles * (uint32_t)(QG * kTile * sizeof(typename St::TG));
+            return OwnedBufDst<St, QF, QG>(buffer_rsrc(a.fdst + (size_t)t0 * (QF * kTile), fb),
+                                           buffer_rsrc(a.gdst + (size_t)t0 * (QG * kTile), gb), fb, gb,
+                                           x + row0 - t0 * kTile, own);
+        }
+    };
     // Row y of step j feeds a stored result only inside the dependency cone
     // of the segment, rows y0 - (NS - j) .. y0 + rows - 1 + (NS - j) (for
     // j = NS the segment itself); elsewhere (while the step pipeline fills
@@ -900,29 +911,23 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
             const Neighbours nb = neighbours(g, x, yy, 0);
             const RegSrc<St, QF, QG> src{fs[j - 2][st(3)], fs[j - 2][st(2)], fs[j - 2][st(1)],
                                          gs[j - 2][st(3)], gs[j - 2][st(2)], gs[j - 2][st(1)]};
-            const PtrFlux2 fx{a.flux, a.slot[(tp + j) & 1], own};
+            const BufFlux2 fx{rflux, a.slot[(tp + j) & 1], a.flux_bytes, own};
             if constexpr (j == NS) {
-                if constexpr (O32) {
-                    // The update runs only on the segment's rows (needed(NS, y)
-                    // is exactly them); the stores always issue, from zeros
-                    // and to the dropped offset elsewhere.
-                    typename St::TF ef[QF];
-                    typename St::TG eg[QG];
-                    if (needed(NS, yj)) {
-                        const bool ok = step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, EncDst<St, QF, QG>{ef, eg}, fx);
-                        if constexpr (Report) bad = bad || (own && !ok);
-                    } else {
-                        static_for<0, QF>([&](auto ic) { ef[decltype(ic)::value] = typename St::TF{}; });
-                        static_for<0, QG>([&](auto ic) { eg[decltype(ic)::value] = typename St::TG{}; });
-                    }
-                    const OwnedBufDst<St, QF, QG> dst(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, own);
-                    static_for<0, QF>([&](auto ic) { dst.sf(decltype(ic)::value, ef[decltype(ic)::value]); });
-                    static_for<0, QG>([&](auto ic) { dst.sg(decltype(ic)::value, eg[decltype(ic)::value]); });
-                } else {
-                    const OwnedGlobalDst<St, QF, QG> dst(a.fdst, a.gdst, x + g.nx * yy, own);
-                    const bool ok = step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                // The update runs only on the segment's rows (needed(NS, y)
+                // is exactly them); the stores always issue, from zeros and
+                // to the dropped offset elsewhere.
+                typename St::TF ef[QF];
+                typename St::TG eg[QG];
+                if (needed(NS, yj)) {
+                    const bool ok = step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, EncDst<St, QF, QG>{ef, eg}, fx);
                     if constexpr (Report) bad = bad || (own && !ok);
+                } else {
+                    static_for<0, QF>([&](auto ic) { ef[decltype(ic)::value] = typename St::TF{}; });
+                    static_for<0, QG>([&](auto ic) { eg[decltype(ic)::value] = typename St::TG{}; });
                 }
+                const OwnedBufDst<St, QF, QG> dst = row_dst(x, yy, own);
+                static_for<0, QF>([&](auto ic) { dst.sf(decltype(ic)::value, ef[decltype(ic)::value]); });
+                static_for<0, QG>([&](auto ic) { dst.sg(decltype(ic)::value, eg[decltype(ic)::value]); });
             } else if (needed(j, yj)) {
                 const RegDst<St, QF, QG> dst{fs[j - 1][st(0)], gs[j - 1][st(0)]};
                 step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
@@ -939,7 +944,7 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
             const RegDst<St, QF, QG> dst{fs[0][st(0)], gs[0][st(0)]};
             const bool own = own_col && y1 >= y0 && y1 < y0 + rows;
             step_node<2, St, Wl>(g, a.c, nb, ucol, yy, 0u, src, dst,
-                                 PtrFlux2{a.flux, a.slot[(tp + 1) & 1], own});
+                                 BufFlux2{rflux, a.slot[(tp + 1) & 1], a.flux_bytes, own});
         }
     };
     // step NS reaches row y0 + rows - 1 at k = rows + 3 NS - 2 + D; the

@@ -435,6 +435,14 @@ bool fits_o32(const lbm_ctx* c) {
     return Np * qf_of(c->p.dim) * elem_f(c->p.storage) < lim && Np * qg_of(c->p.dim) * elem_g(c->p.storage) < lim;
 }
 
+// the streaming kernels address the wall-flux area and (for arrays of 4 GiB
+// or more) one row of populations with 32-bit byte offsets
+bool streamable(const lbm_ctx* c) {
+    const size_t lim = ((size_t)1 << 32) - 65536;
+    const size_t row = ((size_t)c->geo.nx / kTile + 2) * kTile * qf_of(c->p.dim) * 8;
+    return 2 * c->lay.flux_doubles * sizeof(double) < lim && row < lim;
+}
+
 #ifndef LBM_STREAM_WAVES
 #define LBM_STREAM_WAVES 4
 #endif
@@ -483,6 +491,7 @@ template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
     a.flux = c->flux(0, 0);
     a.slot[0] = 0;
     a.slot[1] = (uint32_t)c->lay.flux_doubles;
+    a.flux_bytes = (uint32_t)(2 * c->lay.flux_doubles * sizeof(double));
     for (int64_t s = 0; s < k; ++s) {
         const auto A = pops<St>(c, c->cur), B = pops<St>(c, 1 - c->cur);
         a.fsrc = A.f;
@@ -671,17 +680,18 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         using St = decltype(stc);
         if constexpr (DIM == 2) {
             constexpr bool deep = sizeof(typename St::R) == 4;  // FP64: at most two (kMaxStepsFp64)
+            const int32_t spl = streamable(c) ? c->steps_per_launch : 1;
             if constexpr (deep) {
-                if (c->steps_per_launch == 4 && n >= 4) {
+                if (spl == 4 && n >= 4) {
                     stream_launches<St, 4, 0>(c, n / 4);
                     n -= n / 4 * 4;
                 }
-                if (c->steps_per_launch >= 3 && n >= 3) {
+                if (spl >= 3 && n >= 3) {
                     stream_launches<St, 3, 0>(c, n / 3);
                     n -= n / 3 * 3;
                 }
             }
-            if (c->steps_per_launch >= 2 && n >= 2) {
+            if (spl >= 2 && n >= 2) {
                 stream_launches<St, 2, LBM_STREAM_AHEAD>(c, n / 2);
                 n -= n / 2 * 2;
             }

@@ -35,7 +35,8 @@ EXPORTS = ["lbm_derive", "lbm_workspace_bytes", "lbm_bytes_per_update",
            "lbm_batch_cavity", "lbm_batch_nusselt", "lbm_batch_unstable",
            "lbm_batch_tune", "lbm_batch_set_config", "lbm_batch_get_config",
            "lbm_batch_set_steps_per_launch", "lbm_batch_get_steps_per_launch",
-           "lbm_batch_time", "lbm_batch_destroy", "lbm_batch_last_error"]
+           "lbm_batch_time", "lbm_batch_destroy", "lbm_batch_last_error",
+           "lbm_probe_bandwidth"]
 
 
 class Params(C.Structure):
@@ -139,6 +140,8 @@ def lib():
         L.lbm_batch_destroy.restype = None
         L.lbm_batch_last_error.argtypes = [P]
         L.lbm_batch_last_error.restype = C.c_char_p
+        L.lbm_probe_bandwidth.argtypes = [C.c_int32, P, P, sz, C.c_int32, C.c_int32, P]
+        L.lbm_probe_bandwidth.restype = C.c_int32
         for name in ("lbm_batch_create", "lbm_batch_init", "lbm_batch_init_fields",
                      "lbm_batch_step", "lbm_batch_cavity", "lbm_batch_nusselt",
                      "lbm_batch_unstable", "lbm_batch_tune", "lbm_batch_set_config",
@@ -152,6 +155,19 @@ def lib():
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
+
+
+PROBE_KINDS = {"copy": 0, "read": 1, "write": 2}
+
+
+def probe_bandwidth(kind: str, src, dst, nbytes: int, per_thread: int, nontemporal: bool, stream):
+    """One launch of the HBM bandwidth probe on `stream` (src and dst are
+    device tensors; src may be None for kind "write")."""
+    st = lib().lbm_probe_bandwidth(PROBE_KINDS[kind], None if src is None else src.data_ptr(),
+                                   dst.data_ptr(), int(nbytes), int(per_thread), int(bool(nontemporal)),
+                                   stream.cuda_stream)
+    if st != 0:
+        raise LBMError(st, "lbm_probe_bandwidth rejected its arguments or failed to launch")
 
 
 def _dp(a):

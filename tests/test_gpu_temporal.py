@@ -18,10 +18,12 @@ from paper_2211_03160_amd import lbm, workloads as W
 pytestmark = pytest.mark.gpu
 
 STORAGES = ["fp32", "fp64", "fp16", "bf16", "mixed"]
-# (70, 1000) has segments clear of both walls next to ones that touch them,
-# so wavefronts run both the wall-free and the general sweep
+# (200, 1000): its inner strips and segments clear every wall (a strip
+# needs about 116 columns to clear both x walls at four steps per launch),
+# so in the walled layouts wavefronts without wall rules run next to ones
+# with them; in the periodic box every unit takes the wall-free sweep
 SHAPES = [(129, 129), (67, 45), (64, 19), (65, 20), (5, 7), (2, 2), (300, 3), (7, 200), (1, 33), (40, 1),
-          (70, 1000)]
+          (200, 1000)]
 
 
 def _layouts(shape, storage):
@@ -101,26 +103,42 @@ def test_steps_per_launch_arguments():
     assert c2.steps_per_launch == 3
 
 
-def test_multi_step_beyond_4gib_arrays():
-    """FP64 8193^2: each population array exceeds 4 GiB, which takes the
-    streaming kernels' 64-bit addressing path (plain stores under a branch
-    instead of buffer stores).  Moments and wall fluxes must agree bitwise
-    after 5 steps with one and two steps per launch (FP64 runs two at
-    most)."""
+# Shapes whose population arrays (f, or g in the mixed mode) exceed 4 GiB,
+# which takes the streaming kernels' 64-bit addressing path: stores through
+# a buffer resource based at the first tile of each row.
+BIG = [("fp64", (8193, 8193)), ("fp32", (12289, 12289)), ("mixed", (14849, 14849)),
+       ("fp16", (15489, 15489)), ("bf16", (15489, 15489))]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("storage,shape", BIG)
+def test_multi_step_beyond_4gib_arrays(storage, shape):
+    """Moments and wall fluxes agree bitwise after 7 steps with one step per
+    launch and with the storage mode's default (7 = 4 + 3, 3 + 3 + 1 or
+    2 + 2 + 2 + 1 steps per launch)."""
     import torch
-    cfg = W.rayleigh_benard(2, (8193, 8193), ra=1e8, pr=0.71, storage="fp64")
+    cfg = W.rayleigh_benard(2, shape, ra=1e8, pr=0.71, storage=storage)
+    N = shape[0] * shape[1]
+    qf, qg = 9, 5
+    ef = {"fp64": 8, "fp32": 4, "mixed": 2, "fp16": 2, "bf16": 2}[storage]
+    eg = {"fp64": 8, "fp32": 4, "mixed": 4, "fp16": 2, "bf16": 2}[storage]
+    assert max(N * qf * ef, N * qg * eg) > 2 ** 32  # the 64-bit path
     res = []
-    for spl in (1, 2):
-        c = _run(cfg, spl, 5, amp=1e-3)
-        n = c.N
-        rho = torch.empty(n, dtype=torch.float64, device="cuda")
-        u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
-        T = torch.empty(n, dtype=torch.float64, device="cuda")
+    for spl in (1, {"fp64": 2, "fp32": 4, "mixed": 4, "fp16": 3, "bf16": 3}[storage]):
+        print(f"{storage} {shape}: {spl} steps per launch", flush=True)
+        c = _run(cfg, spl, 7, amp=1e-3)
+        rho = torch.empty(N, dtype=torch.float64, device="cuda")
+        u = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+        T = torch.empty(N, dtype=torch.float64, device="cuda")
         c._check(lbm.lib().lbm_fields(c._h, rho.data_ptr(), u.data_ptr(), T.data_ptr()))
         res.append((rho, u, T, c.wall_flux()))
         del c
         torch.cuda.empty_cache()
-    (r1, u1, t1, w1) = res[0]
-    for (r2, u2, t2, w2) in res[1:]:
-        assert torch.equal(r1, r2) and torch.equal(u1, u2) and torch.equal(t1, t2)
-        assert all(np.array_equal(a, b) for a, b in zip(w1, w2))
+    (r1, u1, t1, w1), (r2, u2, t2, w2) = res
+    for name, a, b in (("rho", r1, r2), ("u", u1, u2), ("T", t1, t2)):
+        if not torch.equal(a, b):
+            bad = torch.nonzero(a != b).flatten()
+            pytest.fail(f"{storage} {shape}: {name} differs at {bad.numel()} entries, first {bad[:8].tolist()}")
+    assert all(np.array_equal(a, b) for a, b in zip(w1, w2))
+    del res
+    torch.cuda.empty_cache()
