@@ -5,13 +5,15 @@ Rayleigh-Benard cell (Ra 1e8, Pr 0.71), W untimed warm-up steps then K timed
 steps, inputs resident in HBM, in the library's default launch mode (four
 steps per launch for FP32 in 2D).  GLUPS = nodes x steps / time / 1e9 (the
 MLUPS definition of Section 2.3, Eq. 10, in units of 1e9).  The same JSON
-line carries the roofline of the dominant kernel (with several steps per
-launch it is bound by vector ALU issue: algorithmic FP32 flops per second
-against the non-packed FP32 peak, with the HBM fraction beside it; with one
-step per launch, algorithmic bytes per launch against the 8 TB/s HBM peak),
-the Nu error of the run against an FP64 GPU run of the same steps, the
-other launch modes and storage forms, the 385^3 D3Q19 + D3Q7 cell, and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+line carries the roofline of the dominant kernel against HBM (the
+algorithmic bytes of one launch, one read and one write of every population
+of every node, over the launch's average duration from HIP events, against
+the 8 TB/s peak and against the copy ceiling this GPU reaches with the
+library's probe kernels, measured first), that launch's vector-ALU figures,
+the Nu error of the run against an FP64 GPU run of the same steps (which
+runs before the headline, with its own roofline), the other launch modes and
+storage forms, the 385^3 D3Q19 + D3Q7 cell, and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
        [--only NAME] [--no-cpu] [--copy-probe] [--oracle-timing]
@@ -199,6 +201,61 @@ def nu_err(nu, ref):
     return max(rel(nu[0], ref[0]), rel(nu[1], ref[1]))
 
 
+def copy_ceiling(nbytes=4 << 30, reps=5):
+    """The HBM ceiling of one-pass streaming on this GPU: the library's
+    probe kernels (copy, read-only, write-only; 1, 2, 4 or 8 16-byte vectors
+    per thread, plain or non-temporal) over `nbytes`, each shape timed with
+    HIP events on the stream it is launched on over `reps` launches after
+    one untimed launch.  Returns the best GB/s of each kind and its shape;
+    a copy counts its bytes twice (read and write)."""
+    import torch
+    from paper_2211_03160_amd import lbm
+    s = torch.cuda.current_stream()
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for kind in ("copy", "read", "write"):
+        best = None
+        for k in (1, 2, 4, 8):
+            for nt in (False, True):
+                a = None if kind == "write" else src
+                lbm.probe_bandwidth(kind, a, dst, nbytes, k, nt, s)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                for _ in range(reps):
+                    lbm.probe_bandwidth(kind, a, dst, nbytes, k, nt, s)
+                e1.record(s)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                gbs = nbytes * (2 if kind == "copy" else 1) / (ms * 1e-3) / 1e9
+                if best is None or gbs > best["gbs"]:
+                    best = {"gbs": round(gbs, 1), "per_thread": k, "nontemporal": nt, "ms": round(ms, 4)}
+        out[kind] = best
+    del src, dst
+    torch.cuda.empty_cache()
+    out["bytes"] = nbytes
+    return out
+
+
+def hbm_roofline(r, nodes, kernel, ceiling_gbs=None):
+    """Roofline of a step kernel against HBM: the algorithmic bytes of one
+    launch (one read and one write of every population of every node)
+    divided by the launch's average duration from HIP events."""
+    spl = r["steps_per_launch"]
+    launch_s = r["ms_per_step"] * spl * 1e-3
+    per_node = r["bytes_per_update"] * spl
+    gbs = nodes * per_node / launch_s / 1e9
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(gbs / PEAK_HBM_GBS, 4), "kernel": kernel, "steps_per_launch": spl,
+           "launch_ms": round(launch_s * 1e3, 4), "bytes_per_node_per_launch": per_node,
+           "bytes_per_lattice_update": r["bytes_per_update"]}
+    if ceiling_gbs:
+        out["copy_ceiling_gbs"] = ceiling_gbs
+        out["frac_of_copy_ceiling"] = round(gbs / ceiling_gbs, 4)
+    return out
+
+
 def cpu_baseline(cfg2d, budget_s=12.0):
     """The FP64 oracle, as it stands, on a strip of the headline cell: the
     full 8193-node rows, 65 rows high, same walls and parameters; steps run
@@ -286,7 +343,7 @@ def main():
     ap.add_argument("--only", default=None, help="comma-separated case names: run those and exit")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a 1 GiB device copy (for counter calibration)")
+                    help="also run three 1 GiB probe copies (for counter calibration)")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time the FP64 oracle on C0 in full and the C1/C2 shapes, then exit")
     args = ap.parse_args()
@@ -325,12 +382,15 @@ def main():
     }
 
     if args.copy_probe:
-        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        # a plain copy of known size for counter calibration: 1 GiB read and
+        # 1 GiB written by the library's probe kernel (4 vectors per thread)
+        x = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
-            y.copy_(x)
+            lbm.probe_bandwidth("copy", x, y, 1 << 30, 4, False, torch.cuda.current_stream())
         torch.cuda.synchronize()
-        log("copy probe: 3 x 1 GiB device copies done")
+        del x, y
+        log("copy probe: 3 x 1 GiB probe copies done")
 
     if args.only:
         for name in args.only.split(","):
@@ -341,42 +401,40 @@ def main():
             log(name, json.dumps(r))
         return
 
+    # The copy ceiling and the FP64 reference run first, so the headline is
+    # not the process's first GPU work.
+    ceil = copy_ceiling()
+    log("copy ceiling", json.dumps(ceil))
+    ref64 = run_case(cases["rb2d_8193_fp64"][0], Wm, K, seed, noise)
+    log("fp64", json.dumps(ref64))
     log(f"headline: 8193^2 D2Q9+D2Q5 FP32, warmup {Wm}, timed {K}")
     head = run_case(cfg32, Wm, K, seed, noise)
     log("fp32", json.dumps(head))
-    ref64 = run_case(cases["rb2d_8193_fp64"][0], Wm, K, seed, noise)
-    log("fp64", json.dumps(ref64))
 
     # The dominant kernel: several steps per launch (K and W are multiples
     # of the steps per launch, so every timed launch is one).  Its
     # algorithmic HBM traffic is one read and one write of all populations
-    # per node and launch; with four steps that is 28 B per update, and the
-    # kernel is bound by vector ALU issue, so the roofline is the FP32 one.
+    # per node and launch: 112 B per node, 28 B per lattice update at four
+    # steps.  The same launch's vector-ALU figures stand beside it (the
+    # kernel's instruction issue is the closer limit).
     N = cfg32["n"][0] * cfg32["n"][1]
     spl = head["steps_per_launch"]
-    bpu = head["bytes_per_update"]
-    launch_s = head["ms_per_step"] * spl * 1e-3
-    hbm_gbs = N * bpu * spl / launch_s / 1e9
-    traffic = read_traffic(spl)
+    kname = f"lbm::stream_kernel<StF32, 4, true, {spl}, 0>" if spl > 1 else "lbm::step_kernel<2, StF32>"
+    roofline = hbm_roofline(head, N, kname, ceil["copy"]["gbs"])
+    roofline["traffic"] = read_traffic(spl)
+    launch_s = roofline["launch_ms"] * 1e-3
     if spl > 1:
         tflops = head["glups"] * FLOPS_PER_UPDATE_2D / 1e3
         # VALU issue slots the launch uses: instructions x 4 cycles per
         # SIMD over 1024 SIMDs at 2.4 GHz, during the HIP-event launch time
         insts = read_valu_instructions() if spl == 4 else None
-        valu_issue = round(insts * 4 / 1024 / 2.4e9 / launch_s, 4) if insts else None
-        roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": PEAK_FP32_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                    "kernel": f"lbm::stream_kernel<StF32, 4, true, {spl}, 0>",
-                    "flops_per_lattice_update": FLOPS_PER_UPDATE_2D,
-                    "frac_of_packed_fp32_peak": round(tflops / PEAK_FP32_PACKED_TFLOPS, 4),
-                    "valu_issue_frac": valu_issue,
-                    "hbm_algorithmic_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / PEAK_HBM_GBS, 4)}
-    else:
-        roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(hbm_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-                    "kernel": "lbm::step_kernel<2, StF32>"}
-    roofline.update({"steps_per_launch": spl, "launch_ms": round(launch_s * 1e3, 4),
-                     "bytes_per_node_per_launch": bpu * spl, "bytes_per_lattice_update": bpu})
+        roofline["valu"] = {
+            "flops_per_lattice_update": FLOPS_PER_UPDATE_2D, "achieved_tflops": round(tflops, 2),
+            "peak_tflops": PEAK_FP32_PACKED_TFLOPS, "frac": round(tflops / PEAK_FP32_PACKED_TFLOPS, 4),
+            "peak_nonpacked_tflops": PEAK_FP32_TFLOPS, "frac_nonpacked": round(tflops / PEAK_FP32_TFLOPS, 4),
+            "issue_frac": round(insts * 4 / 1024 / 2.4e9 / launch_s, 4) if insts else None}
+    ref64["roofline"] = hbm_roofline(ref64, N, f"lbm::stream_kernel<StF64, 4, false, {ref64['steps_per_launch']}, 1>",
+                                     ceil["copy"]["gbs"])
 
     variants = {"rb2d_8193_fp64": {**ref64}}
     for k, name in ((1, "one"), (2, "two")):
@@ -391,7 +449,9 @@ def main():
             r["nu_rel_err_vs_fp64"] = nu_err(r["nu"], ref64["nu"])
             variants[name] = r
             log(name, json.dumps(r))
+        N3 = 385 ** 3
         ref3 = run_case(cases["rb3d_385_fp64"][0], 5, W.C2["steps"], W.C2["seed"], W.C2["noise"])
+        ref3["roofline"] = hbm_roofline(ref3, N3, "lbm::step_kernel<3, StF64>", ceil["copy"]["gbs"])
         variants["rb3d_385_fp64"] = ref3
         log("rb3d_385_fp64", json.dumps(ref3))
         for name in ("rb3d_385_fp32", "rb3d_385_fp16", "rb3d_385_bf16", "rb3d_385_mixed"):
@@ -400,6 +460,7 @@ def main():
             r["nu_rel_err_vs_fp64"] = nu_err(r["nu"], ref3["nu"])
             r["re_rel_err_vs_fp64"] = rel(r["re"], ref3["re"])
             r["hbm_frac"] = r["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
+            r["roofline"] = hbm_roofline(r, N3, "lbm::step_kernel<3, ...>", ceil["copy"]["gbs"])
             variants[name] = r
             log(name, json.dumps(r))
 
@@ -447,6 +508,7 @@ def main():
         "nu": head["nu"],
         "nu_rel_err_vs_fp64": float(f"{nu_err(head['nu'], ref64['nu']):.3g}"),
         "roofline": roofline,
+        "copy_ceiling": ceil,
         "cpu_baseline": cpu,
         "variants": variants,
         "context": {"paper_single_gpu_glups": {"2d_8193": 1.9312, "3d_385": 1.0424},
