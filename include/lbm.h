@@ -211,6 +211,23 @@ lbm_status lbm_wall_flux(lbm_ctx* c, double* last, double* prev);
 /* FP64 reductions over all nodes.  Synchronises.                        */
 lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* d);
 
+/* For callers that cannot allocate device memory or wait on the host (code
+ * under HIP graph capture, tight serving loops): lbm_diagnostics without
+ * the context's workspace scratch and without synchronising.  Enqueues on
+ * the context's stream the same FP64 reductions and writes the values of
+ * lbm_diag, in field order and as doubles (t, mass, energy, umax, nu_vol,
+ * re, nonfinite), to the caller's device buffer d_out[LBM_DIAG_VALUES].
+ * The per-block partial sums live in a scratch array the library keeps per
+ * device (48 KiB, statically, until the process ends); the call allocates
+ * nothing, copies nothing to the host and issues no memset.  Calls that
+ * overlap on one device (from several host threads, or on different
+ * streams) share that scratch and race: the caller serialises them.
+ * LBM_E_INVALID if d_out is NULL or not device memory, LBM_E_STATE before
+ * init.  Non-finite populations are counted in d_out[6], not reported as
+ * LBM_E_UNSTABLE (the call does not wait for the result).              */
+#define LBM_DIAG_VALUES 7
+lbm_status lbm_diagnostics_async(lbm_ctx* c, double* d_out);
+
 /* Checkpoint: the stored populations, the wall-flux history and t.
  * lbm_state_bytes gives the size; export writes it to host memory and
  * synchronises; import reads a buffer exported by a context with the same

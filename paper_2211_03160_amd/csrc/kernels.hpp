@@ -1241,6 +1241,24 @@ __global__ __launch_bounds__(1024) void diag_final_kernel(const double* partial,
     }
 }
 
+// The values of lbm_diag from the reduced sums (mass, energy, sum |u|^2,
+// sum u_g (T - T0), max |u|, nonfinite), in the field order of lbm_diag:
+// t, mass, energy, umax, nu_vol, re, nonfinite.  The same FP64 operations,
+// in the same order, as the host computes them for lbm_diagnostics.
+struct DiagScale {
+    double t, N, H, alpha, nu, dT;
+};
+__global__ __launch_bounds__(64) void diag_values_kernel(const double* sums, DiagScale s, double* out) {
+    if (threadIdx.x != 0) return;
+    out[0] = s.t;
+    out[1] = sums[0];
+    out[2] = sums[1];
+    out[3] = sums[4];
+    out[4] = 1.0 + s.H * (sums[3] / s.N) / (s.alpha * s.dT);
+    out[5] = sqrt(sums[2] / s.N) * s.H / s.nu;
+    out[6] = sums[5];
+}
+
 // per-face wall heat flux sums: block b reduces buffer b (face, slot) in FP64
 struct FaceSumArgs {
     const double* buf[12];

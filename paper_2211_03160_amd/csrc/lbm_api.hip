@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -884,6 +885,80 @@ lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* d) {
     d->re = std::sqrt(v[2] / N) * H / nu;
     d->nonfinite = (int64_t)v[5];
     if (d->nonfinite) return set_err(c->err, LBM_E_UNSTABLE, "%lld non-finite populations", (long long)d->nonfinite);
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ diagnostics, no allocation
+// Scratch of lbm_diagnostics_async: the per-block partial sums of the
+// diagnostics reduction and the reduced sums after them.  Each device the
+// library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (the array's name is a host-side stand-in).
+constexpr int kNoAllocScratchDoubles = (kDiagBlocks + 1) * kDiagVals;  // 48 KiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device, looked up once per
+// device
+lbm_status scratch_of_device(char* err, int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_err(err, LBM_E_UNSUPPORTED, "device %d: the no-allocation scratch covers devices 0 .. %d", dev,
+                       kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(err, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_err(err, LBM_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch");
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_diagnostics_async(lbm_ctx* c, double* d_out) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (!d_out || !is_device_ptr(d_out)) return set_err(c->err, LBM_E_INVALID, "d_out must be device memory");
+    if ((st = require_state(c))) return st;
+    double* ws = nullptr;
+    if ((st = scratch_of_device(c->err, c->device, &ws))) return st;
+    const int nblk = (int)std::min<size_t>(kDiagBlocks, grid_for(c->geo.N));
+    if ((size_t)(nblk + 1) * kDiagVals > (size_t)kNoAllocScratchDoubles)
+        return set_err(c->err, LBM_E_INVALID, "%d reduction blocks exceed the %d-double scratch", nblk,
+                       kNoAllocScratchDoubles);
+    double* sums = ws + (size_t)nblk * kDiagVals;
+    st = dispatch(c, [&](auto dimc, auto stc) -> lbm_status {
+        constexpr int DIM = decltype(dimc)::value;
+        using St = decltype(stc);
+        const auto A = pops<St>(c, c->cur);
+        DiagArgs<St> a{};
+        a.fsrc = A.f;
+        a.gsrc = A.g;
+        a.N = c->geo.N;
+        a.gbeta = c->d.v[LBM_D_GBETA];
+        a.t_base = c->t_base;
+        a.t0 = c->d.v[LBM_D_T0];
+        a.partial = ws;
+        hipLaunchKernelGGL((diag_kernel<DIM, St>), dim3(nblk), dim3(kBlock), 0, c->stream, a);
+        HIP_TRY(c->err, hipGetLastError());
+        return LBM_OK;
+    });
+    if (st) return st;
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(1024), 0, c->stream, (const double*)ws, nblk, sums);
+    HIP_TRY(c->err, hipGetLastError());
+    const DiagScale sc{(double)c->t, (double)c->geo.N, c->d.v[LBM_D_H], c->d.v[LBM_D_ALPHA], c->d.v[LBM_D_NU],
+                       c->p.t_hot - c->p.t_cold};
+    hipLaunchKernelGGL(diag_values_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)sums, sc, d_out);
+    HIP_TRY(c->err, hipGetLastError());
     return LBM_OK;
 }
 

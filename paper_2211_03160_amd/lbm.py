@@ -36,7 +36,8 @@ EXPORTS = ["lbm_derive", "lbm_workspace_bytes", "lbm_bytes_per_update",
            "lbm_batch_tune", "lbm_batch_set_config", "lbm_batch_get_config",
            "lbm_batch_set_steps_per_launch", "lbm_batch_get_steps_per_launch",
            "lbm_batch_time", "lbm_batch_destroy", "lbm_batch_last_error",
-           "lbm_probe_bandwidth"]
+           "lbm_probe_bandwidth", "lbm_diagnostics_async"]
+DIAG_VALUES = 7  # LBM_DIAG_VALUES: t, mass, energy, umax, nu_vol, re, nonfinite
 
 
 class Params(C.Structure):
@@ -142,6 +143,8 @@ def lib():
         L.lbm_batch_last_error.restype = C.c_char_p
         L.lbm_probe_bandwidth.argtypes = [C.c_int32, P, P, sz, C.c_int32, C.c_int32, P]
         L.lbm_probe_bandwidth.restype = C.c_int32
+        L.lbm_diagnostics_async.argtypes = [P, P]
+        L.lbm_diagnostics_async.restype = C.c_int32
         for name in ("lbm_batch_create", "lbm_batch_init", "lbm_batch_init_fields",
                      "lbm_batch_step", "lbm_batch_cavity", "lbm_batch_nusselt",
                      "lbm_batch_unstable", "lbm_batch_tune", "lbm_batch_set_config",
