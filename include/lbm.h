@@ -49,15 +49,21 @@ typedef int32_t lbm_status;
 #define LBM_OK 0
 #define LBM_E_INVALID (-1)     /* bad argument or parameter                */
 #define LBM_E_DEVICE (-2)      /* a HIP call failed                        */
-#define LBM_E_UNSTABLE (-3)    /* non-finite populations at a sync point   */
+#define LBM_E_UNSTABLE (-3)    /* non-finite populations, or a speed above
+                                  the lattice sound speed c_s = 1/sqrt(3),
+                                  found at a sync point                    */
 #define LBM_E_STATE (-4)       /* call out of order                        */
 #define LBM_E_UNSUPPORTED (-5) /* valid request this build cannot serve    */
 
 /* Population storage.  Collision arithmetic is FP32 for every mode except
  * LBM_FP64, which computes in FP64 (the accuracy reference).  Every mode
- * stores the deviations f_i - w_i and g_i - w_i^T T0 (w_i^T: rest-state
- * weights of the thermal equilibrium); the 16-bit modes round them to
- * nearest even.                                                         */
+ * stores deviations from a reference state: f_i - w_i, and g_i - G_i with
+ * G the exact conduction state of the discrete step between the Dirichlet
+ * faces of one axis (the gravity axis first; the linear profile and the
+ * odd part that carries its heat flux), or w_i^T T0 where there is no such
+ * axis (w_i^T: rest-state weights of the thermal equilibrium).  The
+ * 16-bit modes round the deviations to nearest even; FP16 stores them
+ * scaled by 2^14.                                                       */
 #define LBM_FP32 0
 #define LBM_FP64 1
 #define LBM_FP16_SHIFTED 2
@@ -191,7 +197,8 @@ int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
  * rho = sum f, u = (sum e f + F/2)/rho, T = sum g of Section 2.2),
  * computed in FP64 from the stored populations.  Each pointer may be
  * NULL, host or device memory.  Synchronises.  LBM_E_UNSTABLE (after
- * writing the outputs) if any stored population is non-finite.          */
+ * writing the outputs) if any stored population is non-finite or any
+ * node's speed exceeds the lattice sound speed 1/sqrt(3).               */
 lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T);
 
 /* Wall Nusselt numbers, FP64, averaged over the last two steps.  The heat
@@ -208,7 +215,9 @@ lbm_status lbm_nusselt(lbm_ctx* c, double* nu_hot, double* nu_cold);
  * step before (prev[6]); zero for non-Dirichlet faces.  Synchronises.   */
 lbm_status lbm_wall_flux(lbm_ctx* c, double* last, double* prev);
 
-/* FP64 reductions over all nodes.  Synchronises.                        */
+/* FP64 reductions over all nodes.  Synchronises.  LBM_E_UNSTABLE (after
+ * writing *d) if a stored population is non-finite or umax exceeds the
+ * lattice sound speed 1/sqrt(3).                                        */
 lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* d);
 
 /* For callers that cannot allocate device memory or wait on the host (code
@@ -340,7 +349,8 @@ lbm_status lbm_batch_cavity(lbm_batch* b, int32_t k, lbm_ctx** view);
 lbm_status lbm_batch_nusselt(lbm_batch* b, double* nu_hot, double* nu_cold);
 
 /* flags[k] = 1 once cavity k produced a non-finite density or temperature
- * (its divergence does not affect the other cavities).  Synchronises.   */
+ * or a speed above the lattice sound speed 1/sqrt(3) (its divergence does
+ * not affect the other cavities).  Synchronises.                        */
 lbm_status lbm_batch_unstable(lbm_batch* b, int32_t* flags);
 
 /* Autotuner of the one-step kernel: times `steps` one-step launches of

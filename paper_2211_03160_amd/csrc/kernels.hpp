@@ -17,11 +17,20 @@
 // and writes a few contiguous runs of Q x 64 values instead of Q separate
 // streams N apart, which the HBM controllers serve at a higher rate.
 //
-// Every storage mode keeps deviations from the rest state, h_i = f_i - w_i
-// (flow) and h^g_i = g_i - w^T_i T_b (thermal, T_b = T0), and all arithmetic
-// runs on them, so the order-one rest populations never swamp the small
-// non-equilibrium parts: stored as f itself, an FP32 population near w
-// rounds away any deviation below half an ulp of w (~1.5e-8) every step.
+// Every storage mode keeps deviations from a reference state and all
+// arithmetic runs on them, so the order-one reference populations never
+// swamp the small parts that carry the flow and the heat flux: h_i = f_i -
+// w_i (flow, the rest state) and h^g_i = g_i - G_i(x) (thermal), where G is
+// the exact discrete conduction state between the two Dirichlet faces of
+// one axis -- the linear profile T_b(x) = T_lo + (k + 1/2) (T_hi - T_lo)/n
+// at coordinate k along that axis, with the odd part that carries its
+// constant heat flux (a fixed point of the step, Section 2.2's wall rules
+// included) -- or the uniform T0 where no such axis exists.  Stored as f
+// itself, an FP32 population near w rounds away any deviation below half an
+// ulp of w (~1.5e-8) every step; stored relative to T0 alone, a 16-bit g
+// loses the wall heat flux, whose share of the populations (~alpha dT / H)
+// lies below its quantum.  Relative to G the conduction state is exactly
+// zero and the wall links need no constant of their own.
 // With orthogonal bases the collision is applied as an increment:
 //   h+_i = h_i + sum_k M_ki dm_k / |M_k|^2.
 //
@@ -64,10 +73,17 @@ struct E64 {
     __device__ static double dec(T v) { return v; }
     __device__ static T enc(double v) { return v; }
 };
+// FP16 holds the deviations scaled by 2^14 (exact: a power of two), which
+// keeps deviations down to ~4e-9 in its normal range (unscaled, those below
+// 6.1e-5 would be subnormal, with an absolute quantum of 6e-8) while the
+// largest ones (|h| < 1) stay far below its maximum of 65504.
+constexpr float kF16Scale = 16384.0f;
 struct E16 {
     using T = _Float16;
-    __device__ static float dec(T v) { return (float)v; }
-    __device__ static T enc(float v) { return (T)v; }
+    // a fused multiply-add with -0 is the product itself, and lets the
+    // conversion fold into it (v_fma_mix_f32)
+    __device__ static float dec(T v) { return __builtin_fmaf((float)v, 1.0f / kF16Scale, -0.0f); }
+    __device__ static T enc(float v) { return (T)(v * kF16Scale); }
 };
 struct EB16 {  // bfloat16 kept as raw bits
     using T = uint16_t;
@@ -118,16 +134,34 @@ struct Geometry {
 // every kind's rows also share |M_k|^2 (2D), s, b and q come divided by it,
 // which saves the scaling of each relaxed moment before the inverse
 // transform (folded_rates).
+// Temperature of the thermal reference state at a node: T_b = tb0 + tbg k
+// with k the node's coordinate along `axis` (tbg = 0 where the reference is
+// the uniform T0).
+template <class R> struct BaseTemp {
+    R tb0, tbg;
+    int32_t axis;
+};
+template <class R>
+__host__ __device__ __forceinline__ R base_temp(const BaseTemp<R>& b, uint32_t x, uint32_t y, uint32_t z) {
+    const uint32_t k = b.axis == 0 ? x : b.axis == 1 ? y : z;
+    return b.tb0 + b.tbg * (R)k;
+}
+
 template <class R> struct Coef {
     R s[10];     // flow rate per row kind (0 on conserved kinds)
     R b[10];     // 1 - s/2 per row kind
     R q[10];     // thermal rate per row kind
     R a_t;       // thermal equilibrium constant a_T
     R gbeta;     // g beta
-    R t_base;    // T_b
-    R tb_m_t0;   // T_b - T0
-    R abb[6];    // omega (T_w - T_b) on Dirichlet faces
-    double abb_d[6];  // the same in FP64, for the wall heat flux
+    R t0;        // T0 of the buoyancy force
+    BaseTemp<R> bt;  // temperature of the thermal reference state
+    // anti-bounce-back on a Dirichlet face: h_i = abb - h_opp with
+    // abb = abb_a - abb_b T_b, i.e. omega (T_w - T_b) off the reference
+    // axis and 0 on its faces (the reference state meets the rule exactly)
+    R abb_a[6], abb_b[6];
+    // heat entering through one link of a face of the reference axis in the
+    // reference state, FP64 (0 on the other faces)
+    double flux_c[6];
 };
 
 template <int DIM> constexpr bool folded_rates() {
@@ -308,10 +342,11 @@ static_assert(rows_have_parity<Flow<2>>() && rows_have_parity<Flow<3>>() && rows
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-// Returns false if the node's density or temperature is not finite.
+// Returns false if the node's density or temperature is not finite or its
+// speed exceeds the lattice sound speed.
 template <int DIM, class St, class Dst>
 __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R* hg,
-                                              const Coef<typename St::R>& c, const Dst& dst) {
+                                              const Coef<typename St::R>& c, typename St::R tb, const Dst& dst) {
     using R = typename St::R;
     using L = Flow<DIM>;
     using H = Heat<DIM>;
@@ -372,9 +407,9 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
     };
     const R dT = heat_moment(std::integral_constant<int, 0>{});
     const R rho = R(1) + drho;
-    const R T = c.t_base + dT;
+    const R T = tb + dT;
     R F[3] = {R(0), R(0), R(0)};
-    F[DIM - 1] = rho * c.gbeta * (dT + c.tb_m_t0);  // buoyancy, upward
+    F[DIM - 1] = rho * c.gbeta * (dT + (tb - c.t0));  // buoyancy, upward
     const R inv_rho = recip(rho);
     R u[3];
 #pragma unroll
@@ -469,7 +504,10 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
         constexpr int i = decltype(ic)::value;
         dst.sg(i, St::EG::enc(hg[i]));
     });
-    return isfinite(drho + dT);
+    // unstable: a non-finite density or temperature, or a velocity above
+    // the lattice sound speed c_s = 1/sqrt(3)
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return isfinite(drho + dT) && uu <= R(1.0 / 3.0);
 }
 
 // --------------------------------------------------------- store helpers
@@ -590,6 +628,7 @@ __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename
     using L = Flow<DIM>;
     using H = Heat<DIM>;
     R hf[L::Q], hg[H::Q];
+    const R tb = base_temp(c.bt, x, y, z);
     // The gather is free of branches: a link that crosses a wall reads the
     // opposite plane at the node itself (bounce-back) through the same
     // single load, so every load is issued before any result is waited
@@ -616,7 +655,7 @@ __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename
         // otherwise
         wall_abb[i] = i != 0 && out && g.dirichlet[face];
         wall_v[i] = v;
-        hg[i] = wall_abb[i] ? c.abb[face] - v : v;
+        hg[i] = wall_abb[i] ? (c.abb_a[face] - c.abb_b[face] * tb) - v : v;
     });
     if constexpr (Walls)
         static_for<1, H::Q>([&](auto ic) {
@@ -625,9 +664,12 @@ __device__ __forceinline__ bool step_node(const Geometry& g, const Coef<typename
             constexpr int axis = ex != 0 ? 0 : ey != 0 ? 1 : 2;
             constexpr int face = 2 * axis + ((ex + ey + ez) > 0 ? 0 : 1);
             const uint32_t local = axis == 0 ? y + g.ny * z : axis == 1 ? x + g.nx * z : x + g.nx * y;
-            fx.template put<face>(g, local, c.abb_d[face] - 2.0 * (double)wall_v[i], wall_abb[i]);
+            // omega T_w - 2 g+_out in deviation form, from the constant the
+            // rule applied (widened) and the reference state's own flux
+            const double abb = (double)(c.abb_a[face] - c.abb_b[face] * tb);
+            fx.template put<face>(g, local, abb + c.flux_c[face] - 2.0 * (double)wall_v[i], wall_abb[i]);
         });
-    return collide_store<DIM, St>(hf, hg, c, dst);
+    return collide_store<DIM, St>(hf, hg, c, tb, dst);
 }
 
 // the update of node idx of the arrays fsrc/gsrc into fdst/gdst
@@ -760,8 +802,9 @@ template <class St, int QF, int QG> struct OwnedBufDst {
 // branch.  (Under such a branch the register allocator may place the spill
 // of a value that every lane needs later, and a spill store executes for
 // the active lanes only: the other lanes would reload a stale value.)  The
-// stores are issued only by the sweep with wall rules, which runs on the
-// wavefronts next to a wall.
+// store is issued only when some lane of the wavefront is on such a link
+// (a wavefront-uniform branch on the ballot), which happens in the rows
+// and columns next to a Dirichlet wall.
 struct BufFlux2 {
     __amdgpu_buffer_rsrc_t r;
     uint32_t slot;   // first element of the slot
@@ -769,7 +812,9 @@ struct BufFlux2 {
     bool on;
     template <int face> __device__ void put(const Geometry& g, uint32_t local, double v, bool wall) const {
         const uint32_t start = face == 0 ? 0u : face == 1 ? g.ny : face == 2 ? 2u * g.ny : 2u * g.ny + g.nx;
-        buffer_store(v, r, on && wall ? (slot + start + local) * (uint32_t)sizeof(double) : bytes);
+        const bool mine = on && wall;
+        if (__builtin_amdgcn_ballot_w64(mine))
+            buffer_store(v, r, mine ? (slot + start + local) * (uint32_t)sizeof(double) : bytes);
     }
 };
 
@@ -807,8 +852,9 @@ template <class St, int NS> constexpr int stream_waves_per_simd() {
 
 // One wavefront's work unit (strip unit % strips, row segment unit /
 // strips) of a, advancing NS steps from the state of parity tp.  With
-// Report, returns false on a lane that owns a node whose new rho or T is not
-// finite.
+// Report, returns false on a lane that computed, at any of the NS steps, a
+// real node whose new rho or T is not finite or whose speed exceeds the
+// lattice sound speed.
 template <class St, bool O32, int NS, int D, bool Report>
 __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t unit, int32_t tp) {
     using R = typename St::R;
@@ -846,10 +892,10 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
     // arrays when byte offsets fit 32 bits (O32), else based at the first
     // tile of the row (a wavefront-uniform base; a row and its halo span at
     // most nx + 64 nodes), so both forms store without a branch.
+    const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
     auto row_dst = [&](uint32_t x, uint32_t yy, bool own) {
         if constexpr (O32) {
-            return OwnedBufDst<St, QF, QG>(buffer_rsrc(a.fdst, a.f_bytes), buffer_rsrc(a.gdst, a.g_bytes),
-                                           a.f_bytes, a.g_bytes, x + g.nx * yy, own);
+            return OwnedBufDst<St, QF, QG>(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, own);
         } else {
             const uint32_t row0 = g.nx * yy;
             const uint32_t t0 = row0 / kTile, tiles = (row0 + g.nx - 1) / kTile + 1 - t0;
@@ -930,7 +976,12 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
                 static_for<0, QG>([&](auto ic) { dst.sg(decltype(ic)::value, eg[decltype(ic)::value]); });
             } else if (needed(j, yj)) {
                 const RegDst<St, QF, QG> dst{fs[j - 1][st(0)], gs[j - 1][st(0)]};
-                step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                const bool ok = step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, dst, fx);
+                // an intermediate state is checked too where it is a real
+                // node's: a valid lane of step j inside the domain
+                if constexpr (Report)
+                    bad = bad || (!ok && lane >= j && lane <= 63 - j && col >= 0 &&
+                                  (g.periodic[1] || (yj >= 0 && yj <= last)));
             }
         });
         // 3. step 1 on row y1 from the input rows y1 - 1, y1, y1 + 1 (loaded in
@@ -943,8 +994,9 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
                                          gin[in(2 + D)], gin[in(1 + D)], gin[in(D)]};
             const RegDst<St, QF, QG> dst{fs[0][st(0)], gs[0][st(0)]};
             const bool own = own_col && y1 >= y0 && y1 < y0 + rows;
-            step_node<2, St, Wl>(g, a.c, nb, ucol, yy, 0u, src, dst,
-                                 BufFlux2{rflux, a.slot[(tp + 1) & 1], a.flux_bytes, own});
+            const bool ok = step_node<2, St, Wl>(g, a.c, nb, ucol, yy, 0u, src, dst,
+                                                 BufFlux2{rflux, a.slot[(tp + 1) & 1], a.flux_bytes, own});
+            if constexpr (Report) bad = bad || (!ok && lane >= 1 && lane <= 62 && col >= 0 && r1 >= 0);
         }
     };
     // step NS reaches row y0 + rows - 1 at k = rows + 3 NS - 2 + D; the
@@ -997,7 +1049,11 @@ void batch_stream_kernel(BatchStreamArgs<St> b) {
     const uint32_t unit = logical_block(b.blocks_per_xcd) * NWB + wave;
     if (unit >= b.units) return;  // whole wavefront
     const uint32_t k = b.unit_cavity[unit];
-    const StreamArgs<St>& a = b.desc[(uint32_t)b.src * b.count + k];
+    // the cavity's arguments, read through the constant address space
+    // (scalar loads that the kernel's stores cannot invalidate: the tables
+    // do not change during a launch)
+    using CArgs = const __attribute__((address_space(4))) StreamArgs<St>;
+    const StreamArgs<St>& a = *(const StreamArgs<St>*)((CArgs*)b.desc + ((uint32_t)b.src * b.count + k));
     if (!stream_unit<St, O32, NS, D, true>(a, unit - b.unit0[k], b.t_parity)) b.unstable[k] = 1;
 }
 
@@ -1055,6 +1111,7 @@ template <class St> struct InitArgs {
     const double* u;    // mode 1: [DIM][cnt]
     const double* T;    // mode 1: [cnt]
     double w_rest, w_move;  // thermal rest-state weights
+    double delta;           // odd part of the reference state's pre-collision g along its axis
 };
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -1087,7 +1144,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs<St> a) {
         T = a.T[k];
     }
     // equilibria as deviations: f_eq - w = w (drho + rho (3 eu + 4.5 eu^2 - 1.5 uu)),
-    // g_eq - w^T T_b = w^T (T - T_b) + (e.u) T / 2
+    // g_eq - G = w^T (T - T_b) + (e.u) T / 2 - e_a delta (G: the reference
+    // state's pre-collision populations, odd part delta along its axis a)
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     R hf[L::Q], hg[H::Q];
 #pragma unroll
@@ -1095,14 +1153,16 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs<St> a) {
         const double eu = L::ex[i] * u[0] + L::ey[i] * u[1] + L::ez[i] * u[2];
         hf[i] = (R)(L::w[i] * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu)));
     }
-    const double tb = (double)a.c.t_base;
+    const R tbr = base_temp(a.c.bt, x, y, z);
+    const double tb = (double)tbr;
 #pragma unroll
     for (int i = 0; i < H::Q; ++i) {
         const double eu = H::ex[i] * u[0] + H::ey[i] * u[1] + H::ez[i] * u[2];
+        const int ea = a.c.bt.axis == 0 ? H::ex[i] : a.c.bt.axis == 1 ? H::ey[i] : H::ez[i];
         const double wt = i == 0 ? a.w_rest : a.w_move;
-        hg[i] = (R)(wt * (T - tb) + 0.5 * eu * T);
+        hg[i] = (R)(wt * (T - tb) + 0.5 * eu * T - ea * a.delta);
     }
-    collide_store<DIM, St>(hf, hg, a.c, GlobalDst<St, L::Q, H::Q>(a.fdst, a.gdst, idx));
+    collide_store<DIM, St>(hf, hg, a.c, tbr, GlobalDst<St, L::Q, H::Q>(a.fdst, a.gdst, idx));
 }
 
 // ----------------------------------------------------- moments of one node
@@ -1116,8 +1176,8 @@ template <int DIM, class St> struct NodeMoments {
 template <int DIM, class St>
 __device__ __forceinline__ NodeMoments<DIM, St> node_moments(const typename St::TF* fsrc,
                                                              const typename St::TG* gsrc,
-                                                             uint32_t N, uint32_t idx,
-                                                             double gbeta, double t_base,
+                                                             const Geometry& geo, uint32_t idx,
+                                                             double gbeta, const BaseTemp<typename St::R>& bt,
                                                              double t0) {
     using L = Flow<DIM>;
     using H = Heat<DIM>;
@@ -1140,8 +1200,10 @@ __device__ __forceinline__ NodeMoments<DIM, St> node_moments(const typename St::
         bad += !isfinite(h);
         dT += h;
     }
+    uint32_t x, y, z;
+    coords(geo, idx, x, y, z);
     m.rho = 1.0 + drho;
-    m.T = t_base + dT;
+    m.T = (double)base_temp(bt, x, y, z) + dT;
     double F[3] = {0.0, 0.0, 0.0};
     F[DIM - 1] = m.rho * gbeta * (m.T - t0);
     for (int a = 0; a < 3; ++a) m.u[a] = (j[a] - 0.5 * F[a]) / m.rho;
@@ -1152,24 +1214,28 @@ __device__ __forceinline__ NodeMoments<DIM, St> node_moments(const typename St::
 template <class St> struct FieldArgs {
     const typename St::TF* fsrc;
     const typename St::TG* gsrc;
-    uint32_t N, n0, cnt;
-    double gbeta, t_base, t0;
+    Geometry geo;
+    uint32_t n0, cnt;
+    double gbeta, t0;
+    BaseTemp<typename St::R> bt;
     double* rho;  // [cnt] or null
     double* u;    // [DIM][cnt] or null
     double* T;    // [cnt] or null
-    unsigned long long* nonfinite;  // atomic counter
+    unsigned long long* nonfinite;  // atomic counters: [0] non-finite populations,
+                                    // [1] nodes faster than c_s = 1/sqrt(3)
 };
 
 template <int DIM, class St>
 __global__ __launch_bounds__(kBlock) void fields_kernel(FieldArgs<St> a) {
     const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= a.cnt) return;
-    const auto m = node_moments<DIM, St>(a.fsrc, a.gsrc, a.N, a.n0 + k, a.gbeta, a.t_base, a.t0);
+    const auto m = node_moments<DIM, St>(a.fsrc, a.gsrc, a.geo, a.n0 + k, a.gbeta, a.bt, a.t0);
     if (a.rho) a.rho[k] = m.rho;
     if (a.T) a.T[k] = m.T;
     if (a.u)
         for (int d = 0; d < DIM; ++d) a.u[(size_t)d * a.cnt + k] = m.u[d];
     if (m.nonfinite) atomicAdd(a.nonfinite, (unsigned long long)m.nonfinite);
+    if (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2] > 1.0 / 3.0) atomicAdd(a.nonfinite + 1, 1ull);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -1201,8 +1267,9 @@ constexpr int kDiagVals = 6;  // mass, energy, sum |u|^2, sum u_g (T - T0), max 
 template <class St> struct DiagArgs {
     const typename St::TF* fsrc;
     const typename St::TG* gsrc;
-    uint32_t N;
-    double gbeta, t_base, t0;
+    Geometry geo;
+    double gbeta, t0;
+    BaseTemp<typename St::R> bt;
     double* partial;  // [gridDim.x][kDiagVals]
 };
 
@@ -1210,8 +1277,8 @@ template <int DIM, class St>
 __global__ __launch_bounds__(kBlock) void diag_kernel(DiagArgs<St> a) {
     __shared__ double lds[kBlock / 64];
     double acc[kDiagVals] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < a.N; idx += gridDim.x * kBlock) {
-        const auto m = node_moments<DIM, St>(a.fsrc, a.gsrc, a.N, idx, a.gbeta, a.t_base, a.t0);
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < a.geo.N; idx += gridDim.x * kBlock) {
+        const auto m = node_moments<DIM, St>(a.fsrc, a.gsrc, a.geo, idx, a.gbeta, a.bt, a.t0);
         const double uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
         acc[0] += m.rho;
         acc[1] += m.T;

@@ -196,7 +196,6 @@ struct lbm_ctx {
     int cur;      // population buffer holding the state
     int64_t t;    // time step of the state; -1 before init
     Geometry geo;
-    double t_base;
     int cond_axis;
     bool view;    // a cavity owned by a batch: the batch steps and initialises it
     int32_t steps_per_launch;  // lbm_step: 1, or 2 (two-step tiles, 2D)
@@ -220,6 +219,39 @@ struct lbm_ctx {
     } while (0)
 
 namespace {
+
+// The thermal reference state G the stored g deviations are taken from:
+// the exact conduction state of the discrete step between the two Dirichlet
+// faces of the context's conduction axis a (n nodes, walls half a link
+// outside), T_b(k) = T_lo + (k + 1/2) gr with gr = (T_hi - T_lo)/n.  Its
+// populations are w_i T_b plus an odd part along a: pre-collision
+// +/-delta on the two populations along +/-a, (1 - q_j) times that after
+// the collision.  Streaming maps the post-collision state at k - 1 onto the
+// pre-collision one at k when w gr + q_j delta = 0, so delta = -w gr / q_j
+// (w: moving thermal weight, q_j: flux relaxation rate); the
+// anti-bounce-back rule of Section 2.2 then holds exactly at both walls,
+// and each wall link carries the conduction flux -alpha gr into the fluid
+// at the T_lo face (alpha = 2 w (1/q_j - 1/2)), +alpha gr at the T_hi face.
+// Without a conduction axis G is the uniform rest state w_i T0.
+struct Reference {
+    int axis;            // -1: uniform T0
+    double tb0, tbg;     // T_b(k) = tb0 + tbg k
+    double delta;        // odd part of the pre-collision populations along the axis
+    double flux_lo;      // heat entering through one link of the T_lo face
+};
+Reference reference_state(const lbm_ctx* c) {
+    const double* v = c->d.v;
+    Reference r{c->cond_axis, v[LBM_D_T0], 0.0, 0.0, 0.0};
+    if (r.axis < 0) return r;
+    const double t_lo = c->p.t_wall[2 * r.axis], t_hi = c->p.t_wall[2 * r.axis + 1];
+    const double gr = (t_hi - t_lo) / c->p.n[r.axis];
+    const double w = 0.5 * v[LBM_D_OMEGA], qj = v[LBM_D_Q_J];
+    r.tb0 = t_lo + 0.5 * gr;
+    r.tbg = gr;
+    r.delta = -w * gr / qj;
+    r.flux_lo = -2.0 * w * (1.0 / qj - 0.5) * gr;
+    return r;
+}
 
 template <class R> Coef<R> make_coef(const lbm_ctx* c) {
     Coef<R> k{};
@@ -255,12 +287,22 @@ template <class R> Coef<R> make_coef(const lbm_ctx* c) {
     }
     k.a_t = (R)v[LBM_D_A_T];
     k.gbeta = (R)v[LBM_D_GBETA];
-    k.t_base = (R)c->t_base;
-    k.tb_m_t0 = (R)(c->t_base - v[LBM_D_T0]);
+    k.t0 = (R)v[LBM_D_T0];
+    const Reference ref = reference_state(c);
+    k.bt.axis = ref.axis < 0 ? 0 : ref.axis;
+    k.bt.tb0 = (R)ref.tb0;
+    k.bt.tbg = (R)ref.tbg;
+    const double omega = v[LBM_D_OMEGA];
     for (int f = 0; f < 6; ++f) {
-        const double a = c->geo.dirichlet[f] ? v[LBM_D_OMEGA] * (c->p.t_wall[f] - c->t_base) : 0.0;
-        k.abb[f] = (R)a;
-        k.abb_d[f] = (double)(R)a;  // the value the kernel applies, widened
+        k.abb_a[f] = k.abb_b[f] = R(0);
+        k.flux_c[f] = 0.0;
+        if (!c->geo.dirichlet[f]) continue;
+        if (f / 2 == ref.axis) {
+            k.flux_c[f] = f % 2 == 0 ? ref.flux_lo : -ref.flux_lo;
+        } else {
+            k.abb_a[f] = (R)(omega * c->p.t_wall[f]);
+            k.abb_b[f] = (R)omega;
+        }
     }
     return k;
 }
@@ -348,6 +390,7 @@ lbm_status launch_init(lbm_ctx* c, int mode, uint32_t n0, uint32_t cnt, uint64_t
         const double at = c->d.v[LBM_D_A_T];
         a.w_rest = DIM == 2 ? Heat<2>::w_rest(at) : Heat<3>::w_rest(at);
         a.w_move = DIM == 2 ? Heat<2>::w_move(at) : Heat<3>::w_move(at);
+        a.delta = reference_state(c).delta;
         hipLaunchKernelGGL((init_kernel<DIM, St>), dim3(grid_for(cnt)), dim3(kBlock), 0, c->stream, a);
         HIP_TRY(c->err, hipGetLastError());
         return LBM_OK;
@@ -581,7 +624,6 @@ lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void
     for (int f = 0; f < 6; ++f) g.dirichlet[f] = f / 2 < p->dim && p->bc[f] == LBM_BC_DIRICHLET;
     const uint32_t blocks = (g.N + kBlock - 1) / kBlock;
     g.blocks_per_xcd = (blocks + kXcd - 1) / kXcd;
-    c->t_base = d.v[LBM_D_T0];  // thermal populations are stored as g - w^T T0
     c->cond_axis = -1;
     const int order[3] = {p->dim - 1, 0, 1};
     for (int k = 0; k < 3 && c->cond_axis < 0; ++k) {
@@ -739,9 +781,10 @@ lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T) {
     if ((st = require_state(c))) return st;
     const int dim = c->p.dim;
     const size_t N = c->geo.N;
-    // counter in the tail of the reduction area, after the diagnostics partials
+    // two counters in the tail of the reduction area, after the diagnostics
+    // partials: non-finite populations, nodes faster than c_s
     unsigned long long* bad = (unsigned long long*)(c->red() + (size_t)kDiagBlocks * kDiagVals + 32);
-    HIP_TRY(c->err, hipMemsetAsync(bad, 0, sizeof(*bad), c->stream));
+    HIP_TRY(c->err, hipMemsetAsync(bad, 0, 2 * sizeof(*bad), c->stream));
     const bool dev_rho = is_device_ptr(rho), dev_u = is_device_ptr(u), dev_T = is_device_ptr(T);
     const bool all_dev = (!rho || dev_rho) && (!u || dev_u) && (!T || dev_T);
     st = dispatch(c, [&](auto dimc, auto stc) -> lbm_status {
@@ -751,9 +794,9 @@ lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T) {
         FieldArgs<St> a{};
         a.fsrc = A.f;
         a.gsrc = A.g;
-        a.N = (uint32_t)N;
+        a.geo = c->geo;
         a.gbeta = c->d.v[LBM_D_GBETA];
-        a.t_base = c->t_base;
+        a.bt = make_coef<typename St::R>(c).bt;
         a.t0 = c->d.v[LBM_D_T0];
         a.nonfinite = bad;
         if (all_dev) {
@@ -790,10 +833,14 @@ lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T) {
         return LBM_OK;
     });
     if (st) return st;
-    unsigned long long nbad = 0;
-    HIP_TRY(c->err, hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long nbad[2] = {0, 0};
+    HIP_TRY(c->err, hipMemcpyAsync(nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c->err, hipStreamSynchronize(c->stream));
-    if (nbad) return set_err(c->err, LBM_E_UNSTABLE, "%llu non-finite populations at t = %lld", nbad, (long long)c->t);
+    if (nbad[0])
+        return set_err(c->err, LBM_E_UNSTABLE, "%llu non-finite populations at t = %lld", nbad[0], (long long)c->t);
+    if (nbad[1])
+        return set_err(c->err, LBM_E_UNSTABLE, "%llu nodes faster than the lattice sound speed at t = %lld", nbad[1],
+                       (long long)c->t);
     return LBM_OK;
 }
 
@@ -850,9 +897,9 @@ static lbm_status run_diag(lbm_ctx* c, double* host6) {
         DiagArgs<St> a{};
         a.fsrc = A.f;
         a.gsrc = A.g;
-        a.N = c->geo.N;
+        a.geo = c->geo;
         a.gbeta = c->d.v[LBM_D_GBETA];
-        a.t_base = c->t_base;
+        a.bt = make_coef<typename St::R>(c).bt;
         a.t0 = c->d.v[LBM_D_T0];
         a.partial = c->red();
         const int nblk = (int)std::min<size_t>(kDiagBlocks, grid_for(c->geo.N));
@@ -885,6 +932,8 @@ lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* d) {
     d->re = std::sqrt(v[2] / N) * H / nu;
     d->nonfinite = (int64_t)v[5];
     if (d->nonfinite) return set_err(c->err, LBM_E_UNSTABLE, "%lld non-finite populations", (long long)d->nonfinite);
+    if (d->umax > 1.0 / std::sqrt(3.0))
+        return set_err(c->err, LBM_E_UNSTABLE, "max |u| = %g exceeds the lattice sound speed", d->umax);
     return LBM_OK;
 }
 
@@ -943,9 +992,9 @@ lbm_status lbm_diagnostics_async(lbm_ctx* c, double* d_out) {
         DiagArgs<St> a{};
         a.fsrc = A.f;
         a.gsrc = A.g;
-        a.N = c->geo.N;
+        a.geo = c->geo;
         a.gbeta = c->d.v[LBM_D_GBETA];
-        a.t_base = c->t_base;
+        a.bt = make_coef<typename St::R>(c).bt;
         a.t0 = c->d.v[LBM_D_T0];
         a.partial = ws;
         hipLaunchKernelGGL((diag_kernel<DIM, St>), dim3(nblk), dim3(kBlock), 0, c->stream, a);
