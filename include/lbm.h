@@ -301,13 +301,19 @@ typedef struct lbm_batch_config {
                             replay it (needs a non-default stream; ignored on
                             the NULL stream)                                  */
     int32_t reserved;    /* 0                                                 */
+    int32_t stream_rows;  /* rows per strip segment of the streaming kernel
+                             (several steps per launch), 8 .. 256; 0: the
+                             single-cavity default of the storage mode        */
+    int32_t stream_waves; /* wavefronts per block of the streaming kernel:
+                             1, 2, 4 or 8; 0: 4                               */
 } lbm_batch_config;
+#define LBM_BATCH_TUNE_MAX 64 /* most timings lbm_batch_tune reports */
 
 /* Host only.  Device workspace bytes for `count` cavities with parameters
  * ps[0..count-1]; 0 if any is invalid or they differ in dim or storage. */
 size_t lbm_batch_workspace_bytes(const lbm_params* ps, int32_t count);
 
-/* count in [1, 65535].  Default config {256, 0, 0}.  d_workspace: device
+/* count in [1, 65535].  Default config {256, 0, 0, 0, 0, 0}.  d_workspace: device
  * pointer, 256-byte aligned, caller-owned, at least
  * lbm_batch_workspace_bytes bytes.                                      */
 lbm_status lbm_batch_create(const lbm_params* ps, int32_t count, void* d_workspace, size_t bytes,
@@ -353,15 +359,22 @@ lbm_status lbm_batch_nusselt(lbm_batch* b, double* nu_hot, double* nu_cold);
  * not affect the other cavities).  Synchronises.                        */
 lbm_status lbm_batch_unstable(lbm_batch* b, int32_t* flags);
 
-/* Autotuner of the one-step kernel: times `steps` one-step launches of
- * each candidate launch shape (block 128/256/512 x grid_per_cu 0/2/4/8)
- * with HIP events on the batch stream and keeps the fastest (graph_steps
- * is left as configured; the streaming kernel's shape is fixed).  The
- * timing steps are real steps: t advances by 12 (steps + 1).  ms_per_step
- * (nullable) receives up to 12 timings, ncand their number.            */
+/* Autotuner: times `steps` launches of each candidate with HIP events on
+ * the batch stream and keeps the fastest per step: the one-step kernel's
+ * launch shapes (block 128/256/512 x grid_per_cu 0/2/4/8) and, where the
+ * batch can stream several steps per launch, the streaming kernel at 2, 3
+ * and 4 steps per launch (FP64: 2) x segment rows 16/24/32/48/64 x 2/4/8
+ * wavefronts per block.  The winner sets the configuration and the steps
+ * per launch (graph_steps is left as configured); results do not depend on
+ * any of them (bitwise).  The timing steps are real steps: t advances by
+ * (steps + 1) x the steps per launch of every candidate.  ms_per_step
+ * (nullable) receives up to LBM_BATCH_TUNE_MAX timings in candidate order,
+ * ncand their number.                                                   */
 lbm_status lbm_batch_tune(lbm_batch* b, int32_t steps, lbm_batch_config* best, double* ms_per_step,
                           int32_t* ncand);
 
+/* LBM_E_INVALID for a field outside its range.  Changing the streaming
+ * shape rewrites the work tables (synchronises the batch stream).       */
 lbm_status lbm_batch_set_config(lbm_batch* b, const lbm_batch_config* cfg);
 lbm_status lbm_batch_get_config(const lbm_batch* b, lbm_batch_config* cfg);
 int64_t lbm_batch_time(const lbm_batch* b);   /* -1 before init          */

@@ -1042,11 +1042,14 @@ template <class St> struct BatchStreamArgs {
     int32_t* unstable;            // per-cavity flag, set on a non-finite node
 };
 
+// NWB bounds the wavefronts per block; a launch may use fewer (any block
+// of blockDim.x / 64 wavefronts).
 template <class St, int NWB, bool O32, int NS, int D>
 __global__ __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(stream_waves_per_simd<St, NS>())))
 void batch_stream_kernel(BatchStreamArgs<St> b) {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t unit = logical_block(b.blocks_per_xcd) * NWB + wave;
+    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t unit = logical_block(b.blocks_per_xcd) * nw + wave;
     if (unit >= b.units) return;  // whole wavefront
     const uint32_t k = b.unit_cavity[unit];
     // the cavity's arguments, read through the constant address space

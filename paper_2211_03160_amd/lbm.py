@@ -63,11 +63,16 @@ class Diag(C.Structure):
 
 class BatchConfig(C.Structure):
     _fields_ = [("block", C.c_int32), ("grid_per_cu", C.c_int32),
-                ("graph_steps", C.c_int32), ("reserved", C.c_int32)]
+                ("graph_steps", C.c_int32), ("reserved", C.c_int32),
+                ("stream_rows", C.c_int32), ("stream_waves", C.c_int32)]
 
     def as_dict(self):
         return {"block": self.block, "grid_per_cu": self.grid_per_cu,
-                "graph_steps": self.graph_steps}
+                "graph_steps": self.graph_steps, "stream_rows": self.stream_rows,
+                "stream_waves": self.stream_waves}
+
+
+BATCH_TUNE_MAX = 64  # LBM_BATCH_TUNE_MAX
 
 
 class LBMError(RuntimeError):
@@ -467,13 +472,16 @@ class Batch:
         self._check(lib().lbm_batch_get_config(self._h, C.byref(c)))
         return c.as_dict()
 
-    def set_config(self, block=256, grid_per_cu=0, graph_steps=0):
-        c = BatchConfig(int(block), int(grid_per_cu), int(graph_steps), 0)
+    def set_config(self, block=256, grid_per_cu=0, graph_steps=0, stream_rows=0, stream_waves=0):
+        c = BatchConfig(int(block), int(grid_per_cu), int(graph_steps), 0, int(stream_rows), int(stream_waves))
         self._check(lib().lbm_batch_set_config(self._h, C.byref(c)))
 
     def tune(self, steps: int = 5):
+        """Autotune (lbm_batch_tune): returns the chosen configuration (its
+        steps per launch is self.steps_per_launch afterwards) and the
+        per-step timings of every candidate, in ms."""
         best = BatchConfig()
-        ms = np.zeros(16)
+        ms = np.zeros(BATCH_TUNE_MAX)
         n = C.c_int32()
         self._check(lib().lbm_batch_tune(self._h, int(steps), C.byref(best), _dp(ms), C.byref(n)))
         return best.as_dict(), ms[: n.value].tolist()

@@ -100,11 +100,34 @@ def test_launch_shapes_give_identical_results(block, grid_per_cu):
     base.step(25)
     b = lbm.Batch(cfgs)
     b.set_config(block=block, grid_per_cu=grid_per_cu)
-    assert b.config() == {"block": block, "grid_per_cu": grid_per_cu, "graph_steps": 0}
+    assert b.config() == {"block": block, "grid_per_cu": grid_per_cu, "graph_steps": 0, "stream_rows": 0,
+                          "stream_waves": 0}
     b.init(seeds, amps)
     b.step(25)
     for k in range(len(cfgs)):
         assert _fields_equal(b.cavity(k).fields(), base.cavity(k).fields())
+
+
+@pytest.mark.parametrize("spl", [3, 4])
+@pytest.mark.parametrize("rows,waves", [(8, 1), (16, 2), (40, 8), (64, 4), (256, 2)])
+def test_streaming_shapes_give_identical_results(spl, rows, waves):
+    """The streaming kernel's segment rows and wavefronts per block (the
+    autotuner's parameters) change nothing in the results."""
+    cfgs = _small_batch("fp32", 2)
+    seeds = list(range(len(cfgs)))
+    amps = [1e-2] * len(cfgs)
+    base = lbm.Batch(cfgs)
+    base.steps_per_launch = 1
+    base.init(seeds, amps)
+    base.step(25)
+    b = lbm.Batch(cfgs)
+    b.steps_per_launch = spl
+    b.set_config(block=256, stream_rows=rows, stream_waves=waves)
+    b.init(seeds, amps)
+    b.step(25)
+    for k in range(len(cfgs)):
+        assert _fields_equal(b.cavity(k).fields(), base.cavity(k).fields()), k
+    assert np.array_equal(np.nan_to_num(b.nusselt()[0]), np.nan_to_num(base.nusselt()[0]))
 
 
 def test_graph_replay_matches_eager():
@@ -161,11 +184,17 @@ def test_autotuner_picks_a_candidate_and_keeps_results():
     b = lbm.Batch(cfgs)
     b.init(seeds, amps)
     best, ms = b.tune(steps=2)
-    assert len(ms) == 12 and all(m > 0 for m in ms)
+    # 12 one-step shapes, then 2/3/4 steps per launch x 5 segment lengths x
+    # 3 block sizes of the streaming kernel
+    assert len(ms) == 12 + 45 and all(m > 0 for m in ms)
     assert best["block"] in (128, 256, 512) and best["grid_per_cu"] in (0, 2, 4, 8)
     assert b.config() == best
+    spl = b.steps_per_launch
+    if spl > 1:
+        assert best["stream_rows"] in (16, 24, 32, 48, 64) and best["stream_waves"] in (2, 4, 8)
+        assert min(ms[12:]) <= min(ms[:12])
     t = b.t
-    assert t == 12 * 3
+    assert t == 12 * 3 + 15 * 3 * (2 + 3 + 4)
     ref = _singles(cfgs, seeds, amps, t + 10)
     b.step(10)
     for k in range(len(cfgs)):
@@ -187,6 +216,9 @@ def test_views_refuse_stepping_and_batch_errors():
         b.set_config(block=100)
     with pytest.raises(lbm.LBMError):
         b.set_config(graph_steps=3)
+    for bad in (dict(stream_rows=5), dict(stream_rows=300), dict(stream_waves=3), dict(stream_waves=16)):
+        with pytest.raises(lbm.LBMError):
+            b.set_config(**bad)
     b.step(1)
     with pytest.raises(lbm.LBMError) as e:
         b.init_fields(0, None, np.zeros((2, 33 * 17)), np.zeros(33 * 17))
