@@ -178,18 +178,20 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
  * does not divide n ends with shorter launches.                         */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
-/* Steps per kernel launch of lbm_step: 1 .. 4 (more than 1 in 2D only).
+/* Steps per kernel launch of lbm_step: 1 .. 4 in 2D, 1 or 2 in 3D.
  * A 2D context starts with the count measured fastest for its storage:
  * 4 (FP32, FP16-f+FP32-g), 3 (FP16, BF16), 2 (FP64); 3D contexts with 1.
- * With k > 1, each wavefront walks down a strip of
- * columns row by row, keeping the last rows of step t and of the
- * intermediate steps in registers, and writes step t+k: the update of every
- * node is the same arithmetic on the same stored values as with 1, so the
- * results are bitwise identical; only the global memory traffic per step
- * drops to 1/k.  A count of steps that k does not divide ends with shorter
- * launches.  LBM_E_INVALID for other values, LBM_E_UNSUPPORTED for k > 1
- * in 3D and for k > 2 with FP64 storage (its deeper register rings do not
- * fit), LBM_E_STATE for a batch member.                                 */
+ * With k > 1 in 2D, each wavefront walks down a strip of columns row by
+ * row, keeping the last rows of step t and of the intermediate steps in
+ * registers, and writes step t+k; in 3D (k = 2) a block walks a 32 x 16
+ * tile of columns along z, keeping three planes of the first step in LDS
+ * and registers.  The update of every node is the same arithmetic on the
+ * same stored values as with 1, so the results are bitwise identical;
+ * only the global memory traffic per step drops.  A count of steps that k
+ * does not divide ends with shorter launches.  LBM_E_INVALID for other
+ * values, LBM_E_UNSUPPORTED for k > 2 in 3D, for k > 1 with FP64 storage in
+ * 3D (its plane ring would not fit the LDS) and for k > 2 with FP64 in 2D
+ * (its deeper register rings do not fit), LBM_E_STATE for a batch member. */
 lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps);
 int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
 

@@ -1388,3 +1388,5 @@ __global__ __launch_bounds__(1024) void batch_face_sum_kernel(BatchFaceArgs a) {
 }
 
 }  // namespace lbm
+
+#include "stream3d.hpp"

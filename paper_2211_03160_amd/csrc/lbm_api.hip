@@ -487,6 +487,14 @@ bool streamable(const lbm_ctx* c) {
     return 2 * c->lay.flux_doubles * sizeof(double) < lim && row < lim;
 }
 
+// the 3D two-step kernel addresses the wall-flux area and two rows of a
+// plane with 32-bit byte offsets
+bool streamable3(const lbm_ctx* c) {
+    const size_t lim = ((size_t)1 << 32) - 65536;
+    return ((size_t)c->geo.nx * 2 / kTile + 3) * kTile * qf_of(3) * 8 < lim &&
+           2 * c->lay.flux_doubles * sizeof(double) < lim;
+}
+
 #ifndef LBM_STREAM_WAVES
 #define LBM_STREAM_WAVES 4
 #endif
@@ -547,6 +555,42 @@ template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
         else hipLaunchKernelGGL((stream_kernel<St, NWB, false, NS, D>), grid, block, 0, c->stream, a);
         c->cur = 1 - c->cur;
         c->t += NS;
+    }
+}
+
+// Planes per z segment of the 3D two-step kernel: each segment repeats the
+// first step on one plane below and one above it, and segments give the
+// launch enough blocks to fill every compute unit several times over.
+#ifndef LBM_STREAM3_PLANES
+#define LBM_STREAM3_PLANES 48
+#endif
+
+// k launches of the 3D two-step kernel, A -> B, advancing t by 2 k
+template <class St> void stream3_launches(lbm_ctx* c, int64_t k) {
+    Stream3Args<St> a{};
+    a.geo = c->geo;
+    a.c = make_coef<typename St::R>(c);
+    a.tiles_x = (c->geo.nx + kT3OutX - 1) / kT3OutX;
+    a.tiles_y = (c->geo.ny + kT3OutY - 1) / kT3OutY;
+    a.seg_planes = LBM_STREAM3_PLANES;
+    a.segs = (c->geo.nz + a.seg_planes - 1) / a.seg_planes;
+    const uint32_t blocks = a.tiles_x * a.tiles_y * a.segs;
+    a.blocks_per_xcd = (blocks + kXcd - 1) / kXcd;
+    a.flux = c->flux(0, 0);
+    a.flux_bytes = (uint32_t)(2 * c->lay.flux_doubles * sizeof(double));
+    const dim3 grid(a.blocks_per_xcd * kXcd), block(kT3Threads);
+    for (int64_t s = 0; s < k; ++s) {
+        const auto A = pops<St>(c, c->cur), B = pops<St>(c, 1 - c->cur);
+        a.fsrc = A.f;
+        a.gsrc = A.g;
+        a.fdst = B.f;
+        a.gdst = B.g;
+        // step j of the launch writes flux slot (t + j) mod 2
+        a.slot1 = (uint32_t)(((c->t + 1) & 1) * c->lay.flux_doubles);
+        a.slot2 = (uint32_t)((c->t & 1) * c->lay.flux_doubles);
+        hipLaunchKernelGGL((stream3_kernel<St>), grid, block, 0, c->stream, a);
+        c->cur = 1 - c->cur;
+        c->t += 2;
     }
 }
 
@@ -738,6 +782,13 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
                 stream_launches<St, 2, LBM_STREAM_AHEAD>(c, n / 2);
                 n -= n / 2 * 2;
             }
+        } else if constexpr (sizeof(typename St::R) == 4) {
+            // 3D: two steps per launch through the LDS plane ring (FP64's
+            // ring would not fit the LDS)
+            if (c->steps_per_launch == 2 && n >= 2 && streamable3(c)) {
+                stream3_launches<St>(c, n / 2);
+                n -= n / 2 * 2;
+            }
         }
         StepArgs<St> a{};
         a.geo = c->geo;
@@ -765,8 +816,10 @@ lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps) {
     if (st) return st;
     if (c->view) return reject_view(c, "lbm_set_steps_per_launch");
     if (steps < 1 || steps > 4) return set_err(c->err, LBM_E_INVALID, "steps per launch must lie in 1 .. 4");
-    if (steps > 1 && c->p.dim != 2)
-        return set_err(c->err, LBM_E_UNSUPPORTED, "several steps per launch are implemented in 2D only");
+    if (steps > 2 && c->p.dim != 2)
+        return set_err(c->err, LBM_E_UNSUPPORTED, "3D runs at most two steps per launch");
+    if (steps > 1 && c->p.dim == 3 && c->p.storage == LBM_FP64)
+        return set_err(c->err, LBM_E_UNSUPPORTED, "3D FP64 runs one step per launch (its plane ring would not fit the LDS)");
     if (steps > kMaxStepsFp64 && c->p.storage == LBM_FP64)
         return set_err(c->err, LBM_E_UNSUPPORTED, "FP64 runs at most %d steps per launch", kMaxStepsFp64);
     c->steps_per_launch = steps;

@@ -65,6 +65,39 @@ def test_multi_step_bitwise(storage, shape):
                             f"first at {bad[:8]}")
 
 
+SHAPES3 = [(17, 19, 21), (33, 31, 50), (5, 7, 9), (40, 16, 3), (2, 2, 2), (31, 15, 100), (65, 29, 31)]
+
+
+def _layouts3(shape, storage):
+    return {
+        "rb": W.rayleigh_benard(3, shape, ra=5e4, pr=0.71, storage=storage),
+        "rb_periodic": W.rayleigh_benard(3, shape, ra=5e4, pr=0.71, lateral="periodic", storage=storage),
+        "side": W.side_heated(3, shape, ra=5e4, pr=0.71, storage=storage),
+        "box": W.periodic_box(3, shape, nu=0.02, alpha=0.03, gbeta=1e-4, storage=storage),
+    }
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16", "mixed"])
+@pytest.mark.parametrize("shape", SHAPES3)
+def test_3d_two_steps_bitwise(storage, shape):
+    """3D, two steps per launch (the LDS plane ring): 9 steps = 4 launches of
+    two + one single step, against 9 single steps; tiles and z segments
+    ragged, periodic and walled axes, every storage with FP32 arithmetic."""
+    for name, cfg in _layouts3(shape, storage).items():
+        if name != "box" and min(shape) < 2:
+            continue
+        one = _run(cfg, 1, 9)
+        two = _run(cfg, 2, 9)
+        assert one.t == two.t == 9
+        a, b = one.export_state(), two.export_state()
+        if a != b:
+            x, y = np.frombuffer(a, np.uint8), np.frombuffer(b, np.uint8)
+            bad = np.flatnonzero(x != y)
+            pytest.fail(f"{name} {shape} {storage}: {bad.size} bytes differ, first at {bad[:8]}")
+        if name == "rb":
+            assert one.nusselt() == two.nusselt()
+
+
 def test_two_step_after_single_steps_and_nusselt():
     """Mixing launch modes mid-run keeps the state and the flux history."""
     cfg = W.rayleigh_benard(2, (257, 129), ra=1e5, pr=0.71, storage="fp32")
@@ -93,12 +126,16 @@ def test_steps_per_launch_arguments():
             c64.steps_per_launch = k
         assert e.value.status == -5
     c3 = lbm.Cavity(W.rayleigh_benard(3, (9, 9, 9), ra=1e4, pr=0.71, storage="fp32"))
-    assert c3.steps_per_launch == 1
-    for k in (2, 3, 4):
+    for k in (3, 4):
         with pytest.raises(lbm.LBMError) as e:
             c3.steps_per_launch = k
         assert e.value.status == -5
+    c3.steps_per_launch = 2
     c3.steps_per_launch = 1
+    c3d = lbm.Cavity(W.rayleigh_benard(3, (9, 9, 9), ra=1e4, pr=0.71, storage="fp64"))
+    with pytest.raises(lbm.LBMError) as e:
+        c3d.steps_per_launch = 2
+    assert e.value.status == -5
     c2.steps_per_launch = 3
     assert c2.steps_per_launch == 3
 
