@@ -76,7 +76,7 @@ lbm_status lbm_nn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n
         return nn_fail(LBM_E_INVALID, "conv3x3_wgrad: bad shape");
     const uint32_t P = (uint32_t)n * h * w;
     uint32_t per = (P + chunks - 1) / chunks;
-    per = (per + 15) / 16 * 16;
+    per = (per + 31) / 32 * 32;  // whole 32-pixel steps of the MFMA
     const uint32_t used = (P + per - 1) / per;  // chunks that hold pixels
     WGradArgs a{x, dz, partial, n, h, w, cin, cout, P, per, used};
     const size_t waves = (size_t)used * 9 * (cout / 16) * ((cin + 63) / 64);

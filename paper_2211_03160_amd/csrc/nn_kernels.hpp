@@ -2,14 +2,17 @@
 //
 // Activations and gradients are BF16 tensors in NHWC order with a channel
 // count that is a multiple of 16; products accumulate in FP32 on the matrix
-// cores (v_mfma_f32_16x16x16_bf16).  A 3x3 convolution is an implicit GEMM:
-// M = output pixels, N = output channels, K = 9 taps x input channels.
-// Operand layout of the 16x16x16 instruction (lane l of a wavefront):
-//   A (16 x 16, rows = M): lane l holds A[l % 16][4 (l / 16) + j], j < 4
-//   B (16 x 16, rows = K): lane l holds B[4 (l / 16) + j][l % 16]
+// cores with gfx950's double-depth instruction v_mfma_f32_16x16x32_bf16.  A
+// 3x3 convolution is an implicit GEMM: M = output pixels, N = output
+// channels, K = 9 taps x input channels (tap-major), taken 32 at a time.
+// Operand layout of the 16x16x32 instruction (lane l of a wavefront):
+//   A (16 x 32, rows = M): lane l holds A[l % 16][8 (l / 16) + j], j < 8
+//   B (32 x 16, rows = K): lane l holds B[8 (l / 16) + j][l % 16]
 //   D (16 x 16 FP32):      lane l holds D[4 (l / 16) + j][l % 16]
-// Weights are kept as [tap][Cout][Cin] so that the four K values of a B
-// fragment are one 8-byte load.
+// Eight consecutive K values of one lane lie in one tap (channel counts
+// are multiples of 8), so each A and B fragment is one 16-byte load; K
+// values past 9 x cin (cin = 16: 144 = 4.5 x 32) are zero.  Weights are
+// kept as [tap][Cout][Cin].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,6 +24,12 @@ namespace nn {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16 bytes = 8 BF16 values
+
+__device__ __forceinline__ v4f mfma32(v4u a, v4u b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 __device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -55,20 +64,23 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     v4f acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int32_t si = pi + tap / 3 - 1, sj = pj + tap % 3 - 1;
-        const bool ok = pin && si >= 0 && si < a.h && sj >= 0 && sj < a.w;
-        const uint16_t* xrow = a.x + ((size_t)((size_t)pn * a.h + (ok ? si : 0)) * a.w + (ok ? sj : 0)) * a.cin;
-        const uint16_t* wtap = a.wt + (size_t)tap * a.cout * a.cin;
-        for (int c0 = 0; c0 < a.cin; c0 += 16) {
-            v4s av = v4s{0, 0, 0, 0};
-            if (ok) av = *(const v4s*)(xrow + c0 + 4 * kg);
+    const uint32_t K = 9u * (uint32_t)a.cin;
+    for (uint32_t k0 = 0; k0 < K; k0 += 32) {
+        // this lane's eight K values: tap, first input channel
+        const uint32_t k = k0 + 8 * kg;
+        const bool kin = k < K;
+        const uint32_t tap = kin ? k / (uint32_t)a.cin : 0, ci0 = kin ? k % (uint32_t)a.cin : 0;
+        const int32_t si = pi + (int32_t)tap / 3 - 1, sj = pj + (int32_t)tap % 3 - 1;
+        const bool ok = kin && pin && si >= 0 && si < a.h && sj >= 0 && sj < a.w;
+        v4u av = v4u{0u, 0u, 0u, 0u};
+        if (ok) av = *(const v4u*)(a.x + ((size_t)((size_t)pn * a.h + si) * a.w + sj) * a.cin + ci0);
+        const uint16_t* wtap = a.wt + (size_t)tap * a.cout * a.cin + ci0;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const uint32_t co = (cg * NT + t) * 16 + m;
-                const v4s bv = *(const v4s*)(wtap + (size_t)co * a.cin + c0 + 4 * kg);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
-            }
+        for (int t = 0; t < NT; ++t) {
+            const uint32_t co = (cg * NT + t) * 16 + m;
+            v4u bv = v4u{0u, 0u, 0u, 0u};
+            if (kin) bv = *(const v4u*)(wtap + (size_t)co * a.cin);
+            acc[t] = mfma32(av, bv, acc[t]);
         }
     }
 #pragma unroll
@@ -104,12 +116,12 @@ struct WGradArgs {
     const uint16_t* dz;  // [P][cout]
     float* partial;      // [chunks][9][cout][cin]
     int32_t n, h, w, cin, cout;
-    uint32_t P, chunk;   // pixels per chunk (multiple of 16)
+    uint32_t P, chunk;   // pixels per chunk (multiple of 32)
     uint32_t chunks;
 };
 
 // dW[tap][co][ci] = sum_p dz[p][co] x[p shifted by tap][ci]: M = co,
-// N = ci (4 tiles per wave), K = pixels of one chunk.
+// N = ci (4 tiles per wave), K = pixels of one chunk, 32 per instruction.
 __global__ __launch_bounds__(256) void wgrad_kernel(WGradArgs a) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t gw = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -128,12 +140,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WGradArgs a) {
     for (int t = 0; t < 4; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
     const uint32_t p_begin = chunk * a.chunk;
     const uint32_t p_end = p_begin + a.chunk < a.P ? p_begin + a.chunk : a.P;
-    for (uint32_t p0 = p_begin; p0 < p_end; p0 += 16) {
-        v4s av;
-        int32_t src[4];
+    for (uint32_t p0 = p_begin; p0 < p_end; p0 += 32) {
+        // K = 32 pixels: this lane's eight are p0 + 8 kg + j
+        uint16_t av[8];
+        int32_t src[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t p = p0 + 4 * kg + j;
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t p = p0 + 8 * kg + j;
             uint16_t v = 0;
             src[j] = -1;
             if (p < p_end) {
@@ -143,16 +156,17 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WGradArgs a) {
                 const int32_t si = pi + di, sj = pj + dj;
                 if (si >= 0 && si < a.h && sj >= 0 && sj < a.w) src[j] = (pn * a.h + si) * a.w + sj;
             }
-            av[j] = (short)v;
+            av[j] = v;
         }
+        const v4u a8 = __builtin_bit_cast(v4u, av);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (t < NTc) {
-                v4s bv;
+                uint16_t bv[8];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bv[j] = src[j] >= 0 ? (short)a.x[(size_t)src[j] * a.cin + (ib * 4 + t) * 16 + m] : (short)0;
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+                for (int j = 0; j < 8; ++j)
+                    bv[j] = src[j] >= 0 ? a.x[(size_t)src[j] * a.cin + (ib * 4 + t) * 16 + m] : (uint16_t)0;
+                acc[t] = mfma32(a8, __builtin_bit_cast(v4u, bv), acc[t]);
             }
         }
     }
