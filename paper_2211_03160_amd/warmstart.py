@@ -6,10 +6,14 @@ developed convective state (T, u_x, u_y).  The lattice Boltzmann run then
 starts from that state (lbm_batch_init_fields) instead of from conduction
 plus noise.  Training data are snapshots of the developed flow produced by
 the solver itself (batched runs); the plain run from the conduction state
-is both the fallback and the judge: the evaluation counts the steps each
-start needs until the windowed mean of the wall Nusselt number stays within
-1% of that run's long-time mean, and the error of the warm run's long-time
-Nu against the plain run's.
+is both the fallback and the judge.  Every held-out cavity runs three
+times: plain, warm, and plain again with another noise seed (the reference,
+so that neither judged run is compared with its own record).  The
+evaluation counts the steps each start needs until the windowed mean of the
+wall Nusselt number stays inside a band around the reference's long-time
+mean (1%, wider for unsteady cells by their measured fluctuation), and the
+error of each start's long-time Nu against the reference, each as a median
+over the held-out cavities with a 95% bootstrap interval.
 
 Grids: the network sees every second node of the cavity (H = 2 Hc - 1 nodes
 become Hc), zero-padded to a multiple of 2^(levels-1); predictions are
@@ -177,27 +181,68 @@ def predict(net, cfgs, levels):
     return [to_full(c, out[k]) for k, c in enumerate(cfgs)]
 
 
+def window_means(h, window):
+    return np.convolve(np.asarray(h, float), np.ones(window) / window, mode="valid")
+
+
 def steps_to_steady(hist, every, ref, window, tol=0.01):
     """First step after which the windowed mean of Nu stays within tol of
     ref; None if it never settles."""
     h = np.asarray(hist)
     if len(h) < window:
         return None
-    wm = np.convolve(h, np.ones(window) / window, mode="valid")
-    ok = np.abs(wm - ref) <= tol * abs(ref)
+    ok = np.abs(window_means(h, window) - ref) <= tol * abs(ref)
     bad = np.nonzero(~ok)[0]
     first = 0 if len(bad) == 0 else bad[-1] + 1
-    if first >= len(wm):
+    if first >= len(ok):
         return None
     return int((first + window) * every)
 
 
-def evaluate(net, cfgs, seeds, steps, every, levels, window):
-    """Plain (conduction + noise) and warm (network) starts of the same
-    cavities in one batch; Nu = (Nu_hot + Nu_cold)/2 every `every` steps."""
+def tail_stats(h, window, tail):
+    """Long-time mean of a Nu record (its last `tail` entries), the relative
+    standard error of that mean (spread of four block means) and the
+    relative spread of the window means inside the tail."""
+    t = np.asarray(h[-tail:], float)
+    mean = float(t.mean())
+    sem = float(np.std([b.mean() for b in np.array_split(t, 4)]) / 2.0) / abs(mean)
+    spread = float(np.std(window_means(t, window))) / abs(mean) if len(t) >= window else 0.0
+    return mean, sem, spread
+
+
+def judge(plain, warm, ref_run, every, window, tail):
+    """Compare a plain and a warm run of one cavity with a third, independent
+    plain run (another noise seed), the reference.  The reference's
+    long-time mean is the target Nu.  A run has settled once its window mean
+    stays inside a band around that target: 1%, or, for unsteady cells whose
+    window means wander by more than that in the developed state, three times
+    the combined spread of the reference's window means and the error of its
+    mean, so that the developed reference itself seldom leaves the band.  A
+    run settled in the reference's state if its own long-time mean agrees
+    within 1% or three combined standard errors (2D cells are multistable:
+    two plain runs with different noise can end in different roll states)."""
+    ref, sem_r, spread_r = tail_stats(ref_run, window, tail)
+    band = max(0.01, 3.0 * math.hypot(spread_r, sem_r))
+    r = {"nu_ref": ref, "nu_ref_rel_sem": sem_r, "band": band}
+    for name, h in (("plain", plain), ("warm", warm)):
+        mean, sem, _ = tail_stats(h, window, tail)
+        err = abs(mean - ref) / abs(ref)
+        r[f"nu_{name}"] = mean
+        r[f"nu_rel_err_{name}"] = err
+        r[f"same_state_{name}"] = bool(err <= max(0.01, 3.0 * math.hypot(sem_r, sem)))
+        r[f"steps_{name}"] = steps_to_steady(h, every, ref, window, tol=band)
+        r[f"steps_{name}_1pct"] = steps_to_steady(h, every, ref, window, tol=0.01)
+    return r
+
+
+def evaluate(net, cfgs, seeds, ref_seeds, steps, every, levels, window):
+    """Three starts of every held-out cavity in one batch: plain (conduction
+    + noise), warm (the network's prediction) and the reference (conduction
+    + noise with another seed); Nu = (Nu_hot + Nu_cold)/2 every `every`
+    steps."""
     n = len(cfgs)
-    b = lbm.Batch(cfgs + cfgs)
-    b.init(list(seeds) + list(seeds), [W.NOISE] * (2 * n))
+    b = lbm.Batch(cfgs * 3)
+    b.init(list(seeds) + list(seeds) + list(ref_seeds), [W.NOISE] * (3 * n))
     for k, (u, T) in enumerate(predict(net, cfgs, levels)):
         b.init_fields(n + k, None, u, T)
     b.set_config(256, 0, every if every % 2 == 0 else 0)
@@ -209,30 +254,13 @@ def evaluate(net, cfgs, seeds, steps, every, levels, window):
         hist.append(0.5 * (hot + cold))
         if len(hist) % max(1, (steps // every) // 10) == 0:
             log(f"  eval t = {b.t} ({time.time() - t0:.1f} s)")
-    hist = np.array(hist)  # [records][2n]
+    hist = np.array(hist)  # [records][3n]
     tail = max(window, (3 * len(hist)) // 10)
     res = []
     for k in range(n):
-        # each run settles on its own long-time mean (convection cells can
-        # settle in different roll states); the final error compares the
-        # warm run's mean with the plain run's
-        ref = float(hist[-tail:, k].mean())
-        warm_final = float(hist[-tail:, n + k].mean())
-        sp = steps_to_steady(hist[:, k], every, ref, window)
-        sw = steps_to_steady(hist[:, n + k], every, warm_final, window)
-        # statistical uncertainty of the plain run's mean: spread of four
-        # block means over the averaging tail
-        blocks = np.array_split(hist[-tail:, k], 4)
-        sem = float(np.std([b.mean() for b in blocks]) / 2.0) / abs(ref)
-        # unsteady cells fluctuate by more than 1% over any window we can
-        # afford: also count steps into a band of 3 standard errors
-        band = max(0.01, 3.0 * sem)
-        bp = steps_to_steady(hist[:, k], every, ref, window, tol=band)
-        bw = steps_to_steady(hist[:, n + k], every, warm_final, window, tol=band)
-        res.append({"ra": cfgs[k]["ra"], "pr": cfgs[k]["pr"], "nu_plain": ref, "nu_warm": warm_final,
-                    "nu_rel_err_warm": abs(warm_final - ref) / abs(ref), "nu_plain_rel_sem": sem,
-                    "steps_plain": sp, "steps_warm": sw, "band": band,
-                    "steps_plain_band": bp, "steps_warm_band": bw})
+        r = {"ra": cfgs[k]["ra"], "pr": cfgs[k]["pr"]}
+        r.update(judge(hist[:, k], hist[:, n + k], hist[:, 2 * n + k], every, window, tail))
+        res.append(r)
     flags = b.unstable()
     return res, int(flags.sum())
 
@@ -266,25 +294,52 @@ def run(H=257, n_train=128, n_eval=16, steps=200000, snap_from=72000, snap_every
     out["loss_history"] = [round(v, 6) for v in hist]
     t2 = time.time()
     eval_cfgs = cavity_cfgs(n_eval, H, ra_range, pr_range, seed + 99991)
-    res, bad = evaluate(net, eval_cfgs, [seed + 5000 + k for k in range(n_eval)], eval_steps,
-                        eval_every, levels, window)
+    res, bad = evaluate(net, eval_cfgs, [seed + 5000 + k for k in range(n_eval)],
+                        [seed + 7000 + k for k in range(n_eval)], eval_steps, eval_every, levels,
+                        window)
     out["eval_s"] = time.time() - t2
     out["unstable_eval_runs"] = bad
     out["eval"] = res
-    sp = [r["steps_plain"] for r in res if r["steps_plain"] is not None and r["steps_warm"] is not None]
-    sw = [r["steps_warm"] for r in res if r["steps_plain"] is not None and r["steps_warm"] is not None]
-    out["median_steps_plain"] = float(np.median(sp)) if sp else None
-    out["median_steps_warm"] = float(np.median(sw)) if sw else None
-    out["mean_steps_saved_fraction"] = float(np.mean([1 - w / p for p, w in zip(sp, sw) if p])) if sp else None
-    out["median_nu_rel_err_warm"] = float(np.median([r["nu_rel_err_warm"] for r in res]))
-    bb = [(r["steps_plain_band"], r["steps_warm_band"]) for r in res
-          if r["steps_plain_band"] is not None and r["steps_warm_band"] is not None]
-    out["median_steps_plain_band"] = float(np.median([p for p, _ in bb])) if bb else None
-    out["median_steps_warm_band"] = float(np.median([w for _, w in bb])) if bb else None
-    out["median_nu_plain_rel_sem"] = float(np.median([r["nu_plain_rel_sem"] for r in res]))
-    out["settled_plain"] = sum(r["steps_plain"] is not None for r in res)
-    out["settled_warm"] = sum(r["steps_warm"] is not None for r in res)
     out["window_steps"] = window * eval_every
+    out["horizon_steps"] = eval_steps
+    out.update(summarize(res, eval_steps, seed))
+    return out
+
+
+def median_ci(values, rng, draws=4000, level=0.95):
+    """Median and a bootstrap confidence interval over the cavities
+    (percentile method, the cavities resampled with replacement)."""
+    v = np.asarray(values, float)
+    if len(v) == 0:
+        return None, None, None
+    meds = np.median(v[rng.integers(0, len(v), (draws, len(v)))], axis=1)
+    lo, hi = np.quantile(meds, [(1 - level) / 2, (1 + level) / 2])
+    return float(np.median(v)), float(lo), float(hi)
+
+
+def summarize(res, horizon, seed):
+    """Medians over the held-out cavities, each with a 95% bootstrap
+    interval: steps saved by the warm start (plain minus warm steps into the
+    band; a run that never settles counts as the horizon) and the Nu error
+    of either start against the reference; plus how many runs settled (band
+    and strict 1%) and how many ended in the reference's state."""
+    rng = np.random.default_rng(seed)
+    cap = lambda s: horizon if s is None else s
+    saved = [cap(r["steps_plain"]) - cap(r["steps_warm"]) for r in res]
+    med, lo, hi = median_ci(saved, rng)
+    out = {"steps_saved_median": med, "steps_saved_ci95": [lo, hi],
+           "warm_faster_fraction": float(np.mean([s > 0 for s in saved])) if saved else None,
+           "cavities": len(res)}
+    for name in ("plain", "warm"):
+        out[f"median_steps_{name}"] = float(np.median([cap(r[f"steps_{name}"]) for r in res]))
+        out[f"settled_{name}"] = sum(r[f"steps_{name}"] is not None for r in res)
+        out[f"settled_{name}_1pct"] = sum(r[f"steps_{name}_1pct"] is not None for r in res)
+        m, a, z = median_ci([r[f"nu_rel_err_{name}"] for r in res], rng)
+        out[f"nu_rel_err_{name}_median"] = m
+        out[f"nu_rel_err_{name}_ci95"] = [a, z]
+        out[f"same_state_{name}"] = int(sum(r[f"same_state_{name}"] for r in res))
+    out["steps_saved_fraction"] = (1.0 - out["median_steps_warm"] / out["median_steps_plain"]
+                                   if out["median_steps_plain"] else None)
     return out
 
 

@@ -1,9 +1,8 @@
 """What the learned warm start gains over the plain run, end to end on the
 GPU at a small, steady-regime size: data from the solver's own batched runs,
-training with the BF16 MFMA network kernels, then plain and warm starts of
-held-out cavities in one batch.  The warm start must reach a steady Nusselt
-number in fewer steps and settle on the plain run's Nu."""
-import numpy as np
+training with the BF16 MFMA network kernels, then plain, warm and reference
+starts of held-out cavities in one batch.  The warm start must reach a
+steady Nusselt number in fewer steps and settle on the reference's Nu."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -17,10 +16,9 @@ def test_warm_start_saves_steps_in_the_steady_regime():
     print({k: v for k, v in out.items() if k not in ("eval", "loss_history")}, flush=True)
     for r in res:
         print(r, flush=True)
-    assert out["loss_history"][-1] < 0.5 * out["loss_history"][0]
-    pairs = [(r["steps_plain"], r["steps_warm"]) for r in res
-             if r["steps_plain"] is not None and r["steps_warm"] is not None]
-    assert len(pairs) >= len(res) // 2
-    assert np.median([w for _, w in pairs]) < 0.7 * np.median([p for p, _ in pairs])
-    assert np.median([r["nu_rel_err_warm"] for r in res]) < 0.01
     assert out["unstable_eval_runs"] == 0
+    assert out["loss_history"][-1] < 0.5 * out["loss_history"][0]
+    assert out["settled_warm_1pct"] >= len(res) // 2
+    assert out["median_steps_warm"] < 0.7 * out["median_steps_plain"]
+    assert out["steps_saved_ci95"][0] > 0
+    assert out["nu_rel_err_warm_median"] < 0.01
