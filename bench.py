@@ -35,12 +35,15 @@ METRIC = "GLUPS & %HBM peak, FP32 vs FP16-store, 8193² D2Q9+D2Q5 / 385³ D3Q19+
 # launch): HBM traffic counters are valid for this hash only
 KERNEL_SOURCES = ["paper_2211_03160_amd/csrc/kernels.hpp", "paper_2211_03160_amd/csrc/lattice.hpp",
                   "paper_2211_03160_amd/csrc/lbm_api.hip"]
-TRAFFIC_FILES = {4: os.path.join(ROOT, "profiles", "stream4_d2q9_fp32_8193_counters.txt"),
+TRAFFIC_FILES = {5: os.path.join(ROOT, "profiles", "stream5_d2q9_fp32_8193_counters.txt"),
                  1: os.path.join(ROOT, "profiles", "step_d2q9_fp32_8193_counters.txt")}
 # FP32 operations per 2D lattice update in the kernels' formulation (adds,
-# subtracts, multiplies and the reciprocal 1 each, fused multiply-adds 2),
-# counted in the one-step kernel, which computes every node once
-FLOPS_PER_UPDATE_2D = 199
+# subtracts, multiplies and the reciprocal 1 each, fused multiply-adds 2):
+# the written-out D2Q9 + D2Q5 collision with its shared terms, its moments
+# and the reference-state temperature, as in the one-step kernel, which
+# computes every node once (loop-invariant products of rates and constants
+# not counted)
+FLOPS_PER_UPDATE_2D = 148
 # non-packed FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
 # x 2.4 GHz.  The build disables packed FP32, whose dual-rate issue gives the
 # published 157.3; both are reported.
@@ -79,9 +82,10 @@ def read_traffic(steps_per_launch):
         return None
 
 
-def read_valu_instructions():
-    """VALU wave instructions per launch of the four-step FP32 kernel from
-    the committed rocprofv3 run, if taken on the current kernel source."""
+def read_valu_instructions(steps_per_launch):
+    """VALU wave instructions per launch of the multi-step FP32 kernel from
+    the committed rocprofv3 run, if taken on the current kernel source at
+    this many steps per launch."""
     path = os.path.join(ROOT, "profiles", "valu_d2q9_fp32_8193.md")
     if not os.path.exists(path):
         return None
@@ -90,7 +94,7 @@ def read_valu_instructions():
         if ":" in line and not line.startswith(("#", "|")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_hash():
+    if kv.get("kernel_source_sha256") != kernel_hash() or kv.get("steps_per_launch") != str(steps_per_launch):
         return None
     try:
         return float(kv["stream_valu_instructions_per_launch"])
@@ -138,7 +142,7 @@ def run_case(cfg, warmup, steps, seed, noise, want_nu=True, steps_per_launch=Non
 def batched_sweep(K, warmup, noise):
     """Config 3: 64 ragged cavities advanced together, the launch shape and
     steps per launch chosen by the library's autotuner (one-step kernel
-    shapes, and the streaming kernel at 2-4 steps per launch x segment rows
+    shapes, and the streaming kernel at 2-5 steps per launch x segment rows
     x wavefronts per block), replayed from a hipGraph; then the same batch
     with one step per launch (the tuned one-step shape).  Both against the
     same 64 cavities run one after another in the single-cavity default
@@ -147,7 +151,7 @@ def batched_sweep(K, warmup, noise):
     from paper_2211_03160_amd import lbm, workloads as W
     cfgs, seeds = W.batched_sweep()
     nodes = sum(c["n"][0] * c["n"][1] for c in cfgs)
-    graph_steps = 24  # a multiple of every steps-per-launch count
+    graph_steps = 60  # a multiple of every steps-per-launch count
 
     def timed(b):
         b.step(warmup)  # captures the graph
@@ -422,9 +426,8 @@ def main():
     # The dominant kernel: several steps per launch (K and W are multiples
     # of the steps per launch, so every timed launch is one).  Its
     # algorithmic HBM traffic is one read and one write of all populations
-    # per node and launch: 112 B per node, 28 B per lattice update at four
-    # steps.  The same launch's vector-ALU figures stand beside it (the
-    # kernel's instruction issue is the closer limit).
+    # per node and launch: 112 B per node, 22.4 B per lattice update at five
+    # steps.  The same launch's vector-ALU figures stand beside it.
     N = cfg32["n"][0] * cfg32["n"][1]
     spl = head["steps_per_launch"]
     kname = f"lbm::stream_kernel<StF32, 4, true, {spl}, 0>" if spl > 1 else "lbm::step_kernel<2, StF32>"
@@ -435,7 +438,7 @@ def main():
         tflops = head["glups"] * FLOPS_PER_UPDATE_2D / 1e3
         # VALU issue slots the launch uses: instructions x 4 cycles per
         # SIMD over 1024 SIMDs at 2.4 GHz, during the HIP-event launch time
-        insts = read_valu_instructions() if spl == 4 else None
+        insts = read_valu_instructions(spl)
         roofline["valu"] = {
             "flops_per_lattice_update": FLOPS_PER_UPDATE_2D, "achieved_tflops": round(tflops, 2),
             "peak_tflops": PEAK_FP32_PACKED_TFLOPS, "frac": round(tflops / PEAK_FP32_PACKED_TFLOPS, 4),
@@ -487,7 +490,7 @@ def main():
         # evaluation all on the GPU, about 80 s)
         from paper_2211_03160_amd import warmstart as WS
         ws = WS.run()
-        variants["warmstart_rb2d_257"] = {k: v for k, v in ws.items() if k not in ("eval", "loss_history")}
+        variants["warmstart_rb2d_257"] = {k: v for k, v in ws.items() if k not in ("eval", "loss_history", "nu_history")}
         log("warmstart_rb2d_257", json.dumps(variants["warmstart_rb2d_257"]))
 
     cpu = None if args.no_cpu else cpu_baseline(cfg32)

@@ -15,9 +15,9 @@
  *     (Section 2.2), or periodic faces.
  * Every time step is one fused pass: pull-streaming (Eqs. 8b, 9b) with the
  * wall rules, the moments, both collisions and the store of the
- * post-collision populations.  In 2D one kernel launch runs two to four
+ * post-collision populations.  In 2D one kernel launch runs two to five
  * such steps (lbm_set_steps_per_launch), keeping the intermediate rows in
- * registers; in 3D one launch runs one step.
+ * registers; in 3D one launch runs one or two.
  *
  * Conventions
  *   - Every function returns an lbm_status (or a documented value); none
@@ -178,9 +178,10 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
  * does not divide n ends with shorter launches.                         */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
-/* Steps per kernel launch of lbm_step: 1 .. 4 in 2D, 1 or 2 in 3D.
- * A 2D context starts with the count measured fastest for its storage:
- * 4 (FP32, FP16-f+FP32-g), 3 (FP16, BF16), 2 (FP64); 3D contexts with 1.
+/* Steps per kernel launch of lbm_step: 1 .. 5 in 2D (5 with FP32 storage
+ * only), 1 or 2 in 3D.  A 2D context starts with the count measured
+ * fastest for its storage: 5 (FP32), 4 (FP16-f+FP32-g, BF16), 3 (FP16),
+ * 2 (FP64); 3D contexts with 1.
  * With k > 1 in 2D, each wavefront walks down a strip of columns row by
  * row, keeping the last rows of step t and of the intermediate steps in
  * registers, and writes step t+k; in 3D (k = 2) a block walks a 32 x 16
@@ -190,8 +191,10 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n);
  * only the global memory traffic per step drops.  A count of steps that k
  * does not divide ends with shorter launches.  LBM_E_INVALID for other
  * values, LBM_E_UNSUPPORTED for k > 2 in 3D, for k > 1 with FP64 storage in
- * 3D (its plane ring would not fit the LDS) and for k > 2 with FP64 in 2D
- * (its deeper register rings do not fit), LBM_E_STATE for a batch member. */
+ * 3D (its plane ring would not fit the LDS), for k > 2 with FP64 in 2D
+ * (its deeper register rings do not fit) and for k = 5 with 16-bit
+ * storage (slower than four there, so not built), LBM_E_STATE for a batch
+ * member. */
 lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps);
 int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
 
@@ -284,7 +287,7 @@ lbm_status lbm_probe_bandwidth(int32_t kind, const void* src, void* dst, size_t 
 /* ------------------------------------------------------------- batches
  * Many independent cavities of different sizes and parameters (same dim
  * and storage) advanced together: every launch of lbm_batch_step updates
- * all nodes of all cavities, by 2-4 steps in 2D (the streaming kernel of
+ * all nodes of all cavities, by 2-5 steps in 2D (the streaming kernel of
  * lbm_set_steps_per_launch, over the work units of every cavity) or by one,
  * with the per-node arithmetic of lbm_step, so each cavity evolves exactly
  * as it would alone (the physics is Section 2.2's, per cavity; batching is
@@ -309,7 +312,7 @@ typedef struct lbm_batch_config {
     int32_t stream_waves; /* wavefronts per block of the streaming kernel:
                              1, 2, 4 or 8; 0: 4                               */
 } lbm_batch_config;
-#define LBM_BATCH_TUNE_MAX 64 /* most timings lbm_batch_tune reports */
+#define LBM_BATCH_TUNE_MAX 80 /* most timings lbm_batch_tune reports */
 
 /* Host only.  Device workspace bytes for `count` cavities with parameters
  * ps[0..count-1]; 0 if any is invalid or they differ in dim or storage. */
@@ -335,13 +338,14 @@ lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t k, const double* rho, con
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
 
 /* Steps per launch of lbm_batch_step: 1 (batch_step_kernel, the shape of
- * lbm_batch_config) or 2..4 (the streaming kernel; 2D batches whose
- * cavities' population arrays are each under 4 GiB).  A batch starts with
- * the count a single cavity of its storage mode starts with, where
- * streaming is available, else 1.  Results do not depend on it (bitwise).
- * LBM_E_INVALID outside 1..4, LBM_E_UNSUPPORTED for k > 1 where streaming
- * is not available and for k > 2 with FP64 storage.  Synchronises the
- * batch stream when the count changes (the work tables are rewritten).  */
+ * lbm_batch_config) or 2..5 (the streaming kernel; 2D batches whose
+ * cavities' population arrays are each under 4 GiB; 5 with FP32 storage
+ * only).  A batch starts with the count a single cavity of its storage
+ * mode starts with, where streaming is available, else 1.  Results do not
+ * depend on it (bitwise).  LBM_E_INVALID outside 1..5, LBM_E_UNSUPPORTED
+ * for k > 1 where streaming is not available, for k > 2 with FP64 storage
+ * and for k = 5 with 16-bit storage.  Synchronises the batch stream when
+ * the count changes (the work tables are rewritten).                    */
 lbm_status lbm_batch_set_steps_per_launch(lbm_batch* b, int32_t steps);
 int32_t lbm_batch_get_steps_per_launch(const lbm_batch* b); /* 0 for NULL */
 
@@ -365,8 +369,8 @@ lbm_status lbm_batch_unstable(lbm_batch* b, int32_t* flags);
  * the batch stream and keeps the fastest per step: the one-step kernel's
  * launch shapes (block 128/256/512 x grid_per_cu 0/2/4/8) and, where the
  * batch can stream several steps per launch, the streaming kernel at 2, 3
- * and 4 steps per launch (FP64: 2) x segment rows 16/24/32/48/64 x 2/4/8
- * wavefronts per block.  The winner sets the configuration and the steps
+ * and 4 steps per launch (FP32: 2 to 5; FP64: 2) x segment rows
+ * 16/24/32/48/64 x 2/4/8 wavefronts per block.  The winner sets the configuration and the steps
  * per launch (graph_steps is left as configured); results do not depend on
  * any of them (bitwise).  The timing steps are real steps: t advances by
  * (steps + 1) x the steps per launch of every candidate.  ms_per_step

@@ -34,7 +34,7 @@
 // With orthogonal bases the collision is applied as an increment:
 //   h+_i = h_i + sum_k M_ki dm_k / |M_k|^2.
 //
-// In 2D, stream_kernel advances two or three steps per launch: each
+// In 2D, stream_kernel advances two to five steps per launch: each
 // wavefront walks down a strip of columns keeping the last rows of the
 // input and of the intermediate steps in registers, so the intermediate
 // states never go to memory; every node update is the same step_node
@@ -280,8 +280,6 @@ __device__ __forceinline__ R force_mom(int k, const R* u, const R* F) {
     }
 }
 
-// Moments, both collisions and the store of one node.  hf/hg hold the
-// pre-collision deviations on entry.
 // Element i of array p.  With O32 the byte offset is formed in 32 bits
 // (valid for arrays under 4 GiB), which lets the load or store take the
 // array base from scalar registers and the offset from one vector register.
@@ -342,10 +340,110 @@ static_assert(rows_have_parity<Flow<2>>() && rows_have_parity<Flow<3>>() && rows
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-// Returns false if the node's density or temperature is not finite or its
-// speed exceeds the lattice sound speed.
+// a * b + c, rounded once
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// The 2D collision (D2Q9 flow, D2Q5 heat) written out: the same moments,
+// equilibria, forcing moments and inverse transforms as the generic form
+// below, with the terms that several rows share formed once.  Velocities:
+// 1 +x, 2 +y, 3 -x, 4 -y, 5 (+x,+y), 6 (-x,+y), 7 (-x,-y), 8 (+x,-y); flow
+// rows rho, e, eps, jx, qx, jy, qy, pxx, pxy; heat rows T, jx, jy, e, pxx.
+// Rates come divided by their rows' |M_k|^2 (folded_rates).  Buoyancy acts
+// along y only, so every F_x term is dropped.
+template <class St, class Dst>
+__device__ __forceinline__ bool collide_store_d2(typename St::R* h, typename St::R* g,
+                                                 const Coef<typename St::R>& c, typename St::R tb,
+                                                 const Dst& dst) {
+    using R = typename St::R;
+    // flow moments from the sums S and differences D of opposite pairs
+    const R S1 = h[1] + h[3], D1 = h[1] - h[3];
+    const R S2 = h[2] + h[4], D2 = h[2] - h[4];
+    const R S5 = h[5] + h[7], D5 = h[5] - h[7];
+    const R S6 = h[6] + h[8], D6 = h[6] - h[8];
+    const R A = S1 + S2, B = S5 + S6;       // axis and diagonal sums
+    const R drho = (h[0] + A) + B;
+    const R m_e = fmar(R(-4), h[0], fmar(R(2), B, -A));    // -4 h0 - A + 2 B
+    const R m_eps = fmar(R(4), h[0], fmar(R(-2), A, B));   // 4 h0 - 2 A + B
+    const R m_pxx = S1 - S2, m_pxy = S5 - S6;
+    const R P = D5 - D6, Qd = D5 + D6;      // diagonal x and y momenta
+    const R jx = D1 + P, jy = D2 + Qd;
+    const R m_qx = fmar(R(-2), D1, P), m_qy = fmar(R(-2), D2, Qd);
+    // heat moments
+    const R Sg1 = g[1] + g[3], Dg1 = g[1] - g[3];
+    const R Sg2 = g[2] + g[4], Dg2 = g[2] - g[4];
+    const R Cg = Sg1 + Sg2;
+    const R dT = g[0] + Cg;
+    const R n_e = fmar(R(-4), g[0], Cg);
+    const R n_pxx = Sg1 - Sg2;
+    // macroscopic fields and the buoyancy force F = (0, Fy)
+    const R rho = R(1) + drho;
+    const R T = tb + dT;
+    const R Fy = rho * c.gbeta * (dT + (tb - c.t0));
+    const R inv_rho = recip(rho);
+    const R ux = jx * inv_rho;
+    const R uy = fmar(R(0.5), Fy, jy) * inv_rho;
+    const R ux2 = ux * ux, uy2 = uy * uy;
+    const R ruu = rho * (ux2 + uy2);
+    const R uF = uy * Fy;
+    // relaxed increments dm_k (already divided by |M_k|^2): -s (m - m_eq)
+    // + b (M F~)_k, with (M F~) = (6 uF, -6 uF, -Fx, -Fy, 2 (u Fx - v Fy),
+    // u Fy + v Fx) on rows e, eps, qx, qy, pxx, pxy, and F / |M_j|^2 on the
+    // momentum rows (they gain exactly F)
+    const R dm_e = fmar(R(6) * c.b[kE], uF, -c.s[kE] * fmar(R(-3), ruu, fmar(R(2), drho, m_e)));
+    const R dm_eps = fmar(R(-6) * c.b[kEps], uF, -c.s[kEps] * fmar(R(3), ruu, m_eps - drho));
+    const R dm_qx = -c.s[kQ] * fmar(rho, ux, m_qx);
+    const R dm_qy = fmar(-c.b[kQ], Fy, -c.s[kQ] * fmar(rho, uy, m_qy));
+    const R dm_pxx = fmar(R(-2) * c.b[kNu], uF, -c.s[kNu] * fmar(-rho, ux2 - uy2, m_pxx));
+    const R dm_pxy = fmar(c.b[kNu], ux * Fy, -c.s[kNu] * fmar(-rho, ux * uy, m_pxy));
+    const R dm_jy = Fy * R(1.0 / 6.0);
+    // inverse transform: h_i += sum_k M_ki dm_k, as even (e) and odd (o)
+    // parts of each opposite pair
+    h[0] = fmar(R(4), dm_eps - dm_e, h[0]);
+    {
+        const R a = fmar(R(-2), dm_eps, -dm_e);  // shared by the axis pairs
+        const R e1 = a + dm_pxx, e2 = a - dm_pxx;
+        const R o2 = fmar(R(-2), dm_qy, dm_jy);
+        const R b = fmar(R(2), dm_e, dm_eps);    // shared by the diagonal pairs
+        const R e5 = b + dm_pxy, e6 = b - dm_pxy;
+        const R q = dm_jy + dm_qy;
+        const R o5 = q + dm_qx, o6 = q - dm_qx;
+        h[1] = fmar(R(-2), dm_qx, h[1] + e1);
+        h[3] = fmar(R(2), dm_qx, h[3] + e1);
+        h[2] = (h[2] + e2) + o2;
+        h[4] = (h[4] + e2) - o2;
+        h[5] = (h[5] + e5) + o5;
+        h[7] = (h[7] + e5) - o5;
+        h[6] = (h[6] + e6) + o6;
+        h[8] = (h[8] + e6) - o6;
+    }
+    // heat: n_eq = (T, u T, v T, a_T dT, 0) in deviation form
+    const R dn_x = -c.q[kJx] * fmar(-ux, T, Dg1);
+    const R dn_y = -c.q[kJy] * fmar(-uy, T, Dg2);
+    const R dn_e = -c.q[kE] * fmar(-c.a_t, dT, n_e);
+    const R dn_p = -c.q[kNu] * n_pxx;
+    g[0] = fmar(R(-4), dn_e, g[0]);
+    {
+        const R e1 = dn_e + dn_p, e2 = dn_e - dn_p;
+        g[1] = (g[1] + e1) + dn_x;
+        g[3] = (g[3] + e1) - dn_x;
+        g[2] = (g[2] + e2) + dn_y;
+        g[4] = (g[4] + e2) - dn_y;
+    }
+    static_for<0, 9>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dst.sf(i, St::EF::enc(h[i]));
+    });
+    static_for<0, 5>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dst.sg(i, St::EG::enc(g[i]));
+    });
+    return isfinite(drho + dT) && ux2 + uy2 <= R(1.0 / 3.0);
+}
+
+// The collision for any basis with opposite pairs (used in 3D).
 template <int DIM, class St, class Dst>
-__device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R* hg,
+__device__ __forceinline__ bool collide_store_nd(typename St::R* hf, typename St::R* hg,
                                               const Coef<typename St::R>& c, typename St::R tb, const Dst& dst) {
     using R = typename St::R;
     using L = Flow<DIM>;
@@ -510,6 +608,16 @@ __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R
     return isfinite(drho + dT) && uu <= R(1.0 / 3.0);
 }
 
+// Moments, both collisions and the store of one node (hf/hg: the
+// pre-collision deviations).  Returns false if the node's density or
+// temperature is not finite or its speed exceeds the lattice sound speed.
+template <int DIM, class St, class Dst>
+__device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R* hg,
+                                              const Coef<typename St::R>& c, typename St::R tb, const Dst& dst) {
+    if constexpr (DIM == 2) return collide_store_d2<St>(hf, hg, c, tb, dst);
+    else return collide_store_nd<DIM, St>(hf, hg, c, tb, dst);
+}
+
 // --------------------------------------------------------- store helpers
 // Raw buffer stores.  A lane whose byte offset is at or beyond the buffer
 // size stores nothing (the hardware drops out-of-range buffer writes), so a
@@ -531,6 +639,19 @@ __device__ __forceinline__ void buffer_store(T v, __amdgpu_buffer_rsrc_t r, uint
     } else {
         using I2 = int __attribute__((ext_vector_type(2)));
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(I2, v), r, (int)offset, 0, 0);
+    }
+}
+
+// Raw buffer load of an in-range offset: the constant part of the offset
+// goes into the instruction (a 32-bit global address offset cannot take it:
+// the sum might wrap).
+template <class T> __device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t offset) {
+    if constexpr (sizeof(T) == 2) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)offset, 0, 0));
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)offset, 0, 0));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)offset, 0, 0));
     }
 }
 
@@ -706,7 +827,7 @@ __device__ __forceinline__ int32_t region_coord(int32_t v, uint32_t n, int32_t p
 
 // ----------------------------- several steps per launch, register rows (2D)
 // A wavefront walks down a strip of 64 - 2 NS columns, one row per
-// iteration, and advances them NS steps (NS = 2 .. 4).  Lane l holds column
+// iteration, and advances them NS steps (NS = 2 .. 5).  Lane l holds column
 // x0 - NS + l.  The last rows of the input state and of every intermediate
 // step stay in registers as decoded values (rounded through the storage
 // type, so exactly what a single step would store and reload); the
@@ -837,9 +958,9 @@ template <class St> struct StreamArgs {
 };
 
 // Register budget (measured): three wavefronts per SIMD (168 registers) for
-// two steps, and for three steps when f and g are both 16-bit (a small
-// spill, outweighed by the third wavefront); two (256 registers) for four
-// steps, for three steps with FP32 populations, and for FP64 arithmetic.
+// two steps, and for three steps when f and g are both 16-bit; two (256
+// registers) for four and five steps (FP32 at five: 249), for three steps
+// with FP32 populations, and for FP64 arithmetic.
 #ifndef LBM_STREAM_WAVES_PER_SIMD
 #define LBM_STREAM_WAVES_PER_SIMD 3
 #endif
@@ -860,7 +981,7 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
     using R = typename St::R;
     constexpr int QF = Flow<2>::Q, QG = Heat<2>::Q;
     constexpr int W = strip_cols<NS>();
-    static_assert(NS >= 2 && NS <= 4, "two to four steps per launch");
+    static_assert(NS >= 2 && NS <= 5, "two to five steps per launch");
     const Geometry& g = a.geo;
     const int lane = (int)(threadIdx.x & 63);
     bool bad = false;
@@ -893,6 +1014,9 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
     // tile of the row (a wavefront-uniform base; a row and its halo span at
     // most nx + 64 nodes), so both forms store without a branch.
     const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.fdst, a.f_bytes), rg = buffer_rsrc(a.gdst, a.g_bytes);
+    // the sources have the sizes of the destinations (the two buffers of a
+    // ping-pong pair)
+    const __amdgpu_buffer_rsrc_t rfs = buffer_rsrc(a.fsrc, a.f_bytes), rgs = buffer_rsrc(a.gsrc, a.g_bytes);
     auto row_dst = [&](uint32_t x, uint32_t yy, bool own) {
         if constexpr (O32) {
             return OwnedBufDst<St, QF, QG>(rf, rg, a.f_bytes, a.g_bytes, x + g.nx * yy, own);
@@ -935,13 +1059,21 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
             const uint32_t row_in = (uint32_t)(rin >= 0 ? rin : min(max(yl, 0), last));
             const uint32_t node = ucol + g.nx * row_in;
             const uint32_t bf = pop_at<QF>(node, 0), bg = pop_at<QG>(node, 0);
+            using TF = typename St::TF;
+            using TG = typename St::TG;
             static_for<0, QF>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                fin[in(0)][i] = St::EF::dec(*elem<O32>(a.fsrc, bf + i * kTile));
+                if constexpr (O32)
+                    fin[in(0)][i] = St::EF::dec(buffer_load<TF>(rfs, (bf + i * kTile) * (uint32_t)sizeof(TF)));
+                else
+                    fin[in(0)][i] = St::EF::dec(a.fsrc[bf + i * kTile]);
             });
             static_for<0, QG>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                gin[in(0)][i] = St::EG::dec(*elem<O32>(a.gsrc, bg + i * kTile));
+                if constexpr (O32)
+                    gin[in(0)][i] = St::EG::dec(buffer_load<TG>(rgs, (bg + i * kTile) * (uint32_t)sizeof(TG)));
+                else
+                    gin[in(0)][i] = St::EG::dec(a.gsrc[bg + i * kTile]);
             });
         }
         const int32_t y1 = yin - 1 - D;  // row of step 1; step j runs on row y1 - 2 (j - 1)
@@ -960,16 +1092,21 @@ __device__ __forceinline__ bool stream_unit(const StreamArgs<St>& a, uint32_t un
             const BufFlux2 fx{rflux, a.slot[(tp + j) & 1], a.flux_bytes, own};
             if constexpr (j == NS) {
                 // The update runs only on the segment's rows (needed(NS, y)
-                // is exactly them); the stores always issue, from zeros and
-                // to the dropped offset elsewhere.
+                // is exactly them); the stores always issue, to the dropped
+                // offset elsewhere.
                 typename St::TF ef[QF];
                 typename St::TG eg[QG];
                 if (needed(NS, yj)) {
                     const bool ok = step_node<2, St, Wl>(g, a.c, nb, x, yy, 0u, src, EncDst<St, QF, QG>{ef, eg}, fx);
                     if constexpr (Report) bad = bad || (own && !ok);
                 } else {
-                    static_for<0, QF>([&](auto ic) { ef[decltype(ic)::value] = typename St::TF{}; });
-                    static_for<0, QG>([&](auto ic) { eg[decltype(ic)::value] = typename St::TG{}; });
+                    // stored to the dropped offset: any value will do, so
+                    // take whatever the registers hold (an empty asm that
+                    // defines them; a constant would cost a move each)
+#pragma unroll
+                    for (int i = 0; i < QF; ++i) asm volatile("" : "=v"(ef[i]));
+#pragma unroll
+                    for (int i = 0; i < QG; ++i) asm volatile("" : "=v"(eg[i]));
                 }
                 const OwnedBufDst<St, QF, QG> dst = row_dst(x, yy, own);
                 static_for<0, QF>([&](auto ic) { dst.sf(decltype(ic)::value, ef[decltype(ic)::value]); });

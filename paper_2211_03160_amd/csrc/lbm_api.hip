@@ -462,13 +462,26 @@ namespace {
 // 39 at two), and at four steps on arrays over 4 GiB the results differed
 // from single steps on the columns next to strip edges.
 constexpr int kMaxStepsFp64 = 2;
+// Five steps per launch only with FP32 populations: with 16-bit ones the
+// five-step kernel ran slower than four (FP16 151 / 161 GLUPS, BF16 177 /
+// 185, FP16-f+FP32-g 165 / 172 at five / four steps), so it is not built
+// for them.
+constexpr int kMaxSteps2d = 5;
+template <class St> constexpr bool five_steps() {
+    return sizeof(typename St::TF) == 4 && sizeof(typename St::TG) == 4 && sizeof(typename St::R) == 4;
+}
 
+// Measured on the 8193^2 cell once the 2D collision was written out with
+// its shared terms (GLUPS, best segment length each): FP32 at three / four /
+// five steps 103 / 149 / 171; FP16 169 / 161 / 151; BF16 169 / 185 / 177;
+// FP16-f+FP32-g 172 (four) / 165 (five).
 int32_t default_steps_per_launch(int32_t storage) {
     switch (storage) {
-    case LBM_FP32: return 4;
+    case LBM_FP32: return 5;
     case LBM_MIXED_F16_G32: return 4;
+    case LBM_BF16_SHIFTED: return 4;
     case LBM_FP64: return 2;
-    default: return 3;  // FP16, BF16
+    default: return 3;  // FP16 (shifted)
     }
 }
 
@@ -514,13 +527,17 @@ bool streamable3(const lbm_ctx* c) {
 // 32 / 64; FP16-f+FP32-g at four: 150 / 165 / 171 / 171 at 16 / 32 / 48 /
 // 64; FP16 at three: 162 / 168 / 164 / 161 at 16 / 32 / 48 / 64, BF16 at
 // three 139 / 147 / 149 / 148.
+// With the written-out 2D collision: FP32 at four steps 149 / 145 / 138 /
+// 130 at 16 / 24 / 32 / 48 rows, at five 162 / 171 / 166 / 158; FP16 at
+// three 169 / 168 at 32 / 48; BF16 at four 185 at 48; FP16-f+FP32-g at
+// four 172 / 170 at 48 / 64.
 template <class St, int NS> constexpr uint32_t stream_seg_rows() {
     constexpr bool f32 = sizeof(typename St::TF) == 4 && sizeof(typename St::TG) == 4;
     constexpr bool f64 = sizeof(typename St::TF) == 8;
     constexpr bool half = sizeof(typename St::TF) == 2 && sizeof(typename St::TG) == 2;
     if constexpr (f64) return NS == 2 ? 16 : 64;
-    else if constexpr (f32) return NS == 4 ? 24 : 16;
-    else if constexpr (half) return NS == 2 ? 40 : NS == 3 ? 32 : 64;
+    else if constexpr (f32) return NS == 5 ? 24 : 16;
+    else if constexpr (half) return NS == 2 ? 40 : NS == 3 ? 32 : 48;
     else return NS == 2 ? 16 : NS == 3 ? 40 : 48;  // FP16 f, FP32 g
 }
 
@@ -768,8 +785,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         if constexpr (DIM == 2) {
             constexpr bool deep = sizeof(typename St::R) == 4;  // FP64: at most two (kMaxStepsFp64)
             const int32_t spl = streamable(c) ? c->steps_per_launch : 1;
+            if constexpr (five_steps<St>()) {
+                if (spl == 5 && n >= 5) {
+                    stream_launches<St, 5, 0>(c, n / 5);
+                    n -= n / 5 * 5;
+                }
+            }
             if constexpr (deep) {
-                if (spl == 4 && n >= 4) {
+                if (spl >= 4 && n >= 4) {
                     stream_launches<St, 4, 0>(c, n / 4);
                     n -= n / 4 * 4;
                 }
@@ -815,13 +838,16 @@ lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps) {
     lbm_status st = enter(c);
     if (st) return st;
     if (c->view) return reject_view(c, "lbm_set_steps_per_launch");
-    if (steps < 1 || steps > 4) return set_err(c->err, LBM_E_INVALID, "steps per launch must lie in 1 .. 4");
+    if (steps < 1 || steps > kMaxSteps2d)
+        return set_err(c->err, LBM_E_INVALID, "steps per launch must lie in 1 .. %d", kMaxSteps2d);
     if (steps > 2 && c->p.dim != 2)
         return set_err(c->err, LBM_E_UNSUPPORTED, "3D runs at most two steps per launch");
     if (steps > 1 && c->p.dim == 3 && c->p.storage == LBM_FP64)
         return set_err(c->err, LBM_E_UNSUPPORTED, "3D FP64 runs one step per launch (its plane ring would not fit the LDS)");
     if (steps > kMaxStepsFp64 && c->p.storage == LBM_FP64)
         return set_err(c->err, LBM_E_UNSUPPORTED, "FP64 runs at most %d steps per launch", kMaxStepsFp64);
+    if (steps == 5 && c->p.storage != LBM_FP32)
+        return set_err(c->err, LBM_E_UNSUPPORTED, "five steps per launch need FP32 storage");
     c->steps_per_launch = steps;
     return LBM_OK;
 }

@@ -72,7 +72,7 @@ class BatchConfig(C.Structure):
                 "stream_waves": self.stream_waves}
 
 
-BATCH_TUNE_MAX = 64  # LBM_BATCH_TUNE_MAX
+BATCH_TUNE_MAX = 80  # LBM_BATCH_TUNE_MAX
 
 
 class LBMError(RuntimeError):

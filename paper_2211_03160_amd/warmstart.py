@@ -199,6 +199,16 @@ def steps_to_steady(hist, every, ref, window, tol=0.01):
     return int((first + window) * every)
 
 
+def steps_to_reach(hist, every, ref, window, tol):
+    """First step at which the windowed mean of Nu is within tol of ref;
+    None if it never gets there."""
+    h = np.asarray(hist)
+    if len(h) < window:
+        return None
+    ok = np.nonzero(np.abs(window_means(h, window) - ref) <= tol * abs(ref))[0]
+    return None if len(ok) == 0 else int((ok[0] + window) * every)
+
+
 def tail_stats(h, window, tail):
     """Long-time mean of a Nu record (its last `tail` entries), the relative
     standard error of that mean (spread of four block means) and the
@@ -213,11 +223,13 @@ def tail_stats(h, window, tail):
 def judge(plain, warm, ref_run, every, window, tail):
     """Compare a plain and a warm run of one cavity with a third, independent
     plain run (another noise seed), the reference.  The reference's
-    long-time mean is the target Nu.  A run has settled once its window mean
-    stays inside a band around that target: 1%, or, for unsteady cells whose
-    window means wander by more than that in the developed state, three times
-    the combined spread of the reference's window means and the error of its
-    mean, so that the developed reference itself seldom leaves the band.  A
+    long-time mean is the target Nu.  The band around that target is 1%, or,
+    for unsteady cells whose window means wander by more than that in the
+    developed state, three times the combined spread of the reference's
+    window means and the error of its mean, so that the developed reference
+    itself seldom leaves it.  A run reaches the developed state when its
+    window mean first enters the band, and has settled once it stays inside
+    (for a chaotic cell the last exit is itself a random event).  A
     run settled in the reference's state if its own long-time mean agrees
     within 1% or three combined standard errors (2D cells are multistable:
     two plain runs with different noise can end in different roll states)."""
@@ -231,6 +243,7 @@ def judge(plain, warm, ref_run, every, window, tail):
         r[f"nu_rel_err_{name}"] = err
         r[f"same_state_{name}"] = bool(err <= max(0.01, 3.0 * math.hypot(sem_r, sem)))
         r[f"steps_{name}"] = steps_to_steady(h, every, ref, window, tol=band)
+        r[f"steps_{name}_reach"] = steps_to_reach(h, every, ref, window, tol=band)
         r[f"steps_{name}_1pct"] = steps_to_steady(h, every, ref, window, tol=0.01)
     return r
 
@@ -262,7 +275,7 @@ def evaluate(net, cfgs, seeds, ref_seeds, steps, every, levels, window):
         r.update(judge(hist[:, k], hist[:, n + k], hist[:, 2 * n + k], every, window, tail))
         res.append(r)
     flags = b.unstable()
-    return res, int(flags.sum())
+    return res, int(flags.sum()), hist
 
 
 def run(H=257, n_train=128, n_eval=16, steps=200000, snap_from=72000, snap_every=8000,
@@ -294,12 +307,14 @@ def run(H=257, n_train=128, n_eval=16, steps=200000, snap_from=72000, snap_every
     out["loss_history"] = [round(v, 6) for v in hist]
     t2 = time.time()
     eval_cfgs = cavity_cfgs(n_eval, H, ra_range, pr_range, seed + 99991)
-    res, bad = evaluate(net, eval_cfgs, [seed + 5000 + k for k in range(n_eval)],
+    res, bad, hist = evaluate(net, eval_cfgs, [seed + 5000 + k for k in range(n_eval)],
                         [seed + 7000 + k for k in range(n_eval)], eval_steps, eval_every, levels,
                         window)
     out["eval_s"] = time.time() - t2
     out["unstable_eval_runs"] = bad
     out["eval"] = res
+    # Nu every eval_every steps: columns plain, warm, reference per cavity
+    out["nu_history"] = [[float(f"{v:.6g}") for v in row] for row in hist.T]
     out["window_steps"] = window * eval_every
     out["horizon_steps"] = eval_steps
     out.update(summarize(res, eval_steps, seed))
@@ -319,19 +334,24 @@ def median_ci(values, rng, draws=4000, level=0.95):
 
 def summarize(res, horizon, seed):
     """Medians over the held-out cavities, each with a 95% bootstrap
-    interval: steps saved by the warm start (plain minus warm steps into the
-    band; a run that never settles counts as the horizon) and the Nu error
+    interval: steps saved by the warm start (plain minus warm steps until
+    the run settles in the band, and until it first reaches it; a run that
+    never does counts as the horizon) and the Nu error
     of either start against the reference; plus how many runs settled (band
     and strict 1%) and how many ended in the reference's state."""
     rng = np.random.default_rng(seed)
     cap = lambda s: horizon if s is None else s
-    saved = [cap(r["steps_plain"]) - cap(r["steps_warm"]) for r in res]
-    med, lo, hi = median_ci(saved, rng)
-    out = {"steps_saved_median": med, "steps_saved_ci95": [lo, hi],
-           "warm_faster_fraction": float(np.mean([s > 0 for s in saved])) if saved else None,
-           "cavities": len(res)}
+    out = {"cavities": len(res)}
+    for kind, suffix in (("", ""), ("reach", "_reach")):
+        saved = [cap(r["steps_plain" + suffix]) - cap(r["steps_warm" + suffix]) for r in res]
+        med, lo, hi = median_ci(saved, rng)
+        tag = "_" + kind if kind else ""
+        out[f"steps_saved{tag}_median"] = med
+        out[f"steps_saved{tag}_ci95"] = [lo, hi]
+        out[f"warm_faster{tag}_fraction"] = float(np.mean([s > 0 for s in saved])) if saved else None
     for name in ("plain", "warm"):
         out[f"median_steps_{name}"] = float(np.median([cap(r[f"steps_{name}"]) for r in res]))
+        out[f"median_steps_{name}_reach"] = float(np.median([cap(r[f"steps_{name}_reach"]) for r in res]))
         out[f"settled_{name}"] = sum(r[f"steps_{name}"] is not None for r in res)
         out[f"settled_{name}_1pct"] = sum(r[f"steps_{name}_1pct"] is not None for r in res)
         m, a, z = median_ci([r[f"nu_rel_err_{name}"] for r in res], rng)
@@ -359,10 +379,9 @@ def main():
         out = run(**QUICK)
     else:
         out = run()
-    s = json.dumps(out)
-    print(s, flush=True)
+    print(json.dumps({k: v for k, v in out.items() if k != "nu_history"}), flush=True)
     if a.out:
-        open(a.out, "w").write(s)
+        open(a.out, "w").write(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -102,4 +102,4 @@ def batched_sweep(count: int = 64, seed: int = SEED, storage: str = "fp32",
     return cfgs, seeds
 
 
-C3 = dict(name="batch64_rb2d", steps=240, warmup=48, noise=NOISE, count=64, seed=SEED)
+C3 = dict(name="batch64_rb2d", steps=240, warmup=120, noise=NOISE, count=64, seed=SEED)

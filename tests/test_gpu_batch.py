@@ -184,9 +184,9 @@ def test_autotuner_picks_a_candidate_and_keeps_results():
     b = lbm.Batch(cfgs)
     b.init(seeds, amps)
     best, ms = b.tune(steps=2)
-    # 12 one-step shapes, then 2/3/4 steps per launch x 5 segment lengths x
-    # 3 block sizes of the streaming kernel
-    assert len(ms) == 12 + 45 and all(m > 0 for m in ms)
+    # 12 one-step shapes, then 2/3/4/5 steps per launch (FP32) x 5 segment
+    # lengths x 3 block sizes of the streaming kernel
+    assert len(ms) == 12 + 60 and all(m > 0 for m in ms)
     assert best["block"] in (128, 256, 512) and best["grid_per_cu"] in (0, 2, 4, 8)
     assert b.config() == best
     spl = b.steps_per_launch
@@ -194,7 +194,7 @@ def test_autotuner_picks_a_candidate_and_keeps_results():
         assert best["stream_rows"] in (16, 24, 32, 48, 64) and best["stream_waves"] in (2, 4, 8)
         assert min(ms[12:]) <= min(ms[:12])
     t = b.t
-    assert t == 12 * 3 + 15 * 3 * (2 + 3 + 4)
+    assert t == 12 * 3 + 15 * 3 * (2 + 3 + 4 + 5)
     ref = _singles(cfgs, seeds, amps, t + 10)
     b.step(10)
     for k in range(len(cfgs)):
@@ -251,16 +251,20 @@ def test_sweep_recipe_runs_and_tunes():
 def test_batch_steps_per_launch_defaults_and_arguments():
     """2D batches start streaming with a single cavity's default count; 3D
     ones with one step per launch and refuse more."""
-    for storage, k in (("fp32", 4), ("mixed", 4), ("fp16", 3), ("bf16", 3), ("fp64", 2)):
+    for storage, k in (("fp32", 5), ("mixed", 4), ("fp16", 3), ("bf16", 4), ("fp64", 2)):
         assert lbm.Batch(_small_batch(storage, 2)).steps_per_launch == k, storage
     b = lbm.Batch(_small_batch("fp32", 2))
-    for bad in (0, 5, -1):
+    for bad in (0, 6, -1):
         with pytest.raises(lbm.LBMError) as e:
             b.steps_per_launch = bad
         assert e.value.status == -1
-    for k in (1, 2, 3, 4):
+    for k in (1, 2, 3, 4, 5):
         b.steps_per_launch = k
         assert b.steps_per_launch == k
+    for storage in ("mixed", "fp16", "bf16"):  # five steps: FP32 storage only
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.Batch(_small_batch(storage, 2)).steps_per_launch = 5
+        assert e.value.status == -5
     b64 = lbm.Batch(_small_batch("fp64", 2))
     with pytest.raises(lbm.LBMError) as e:
         b64.steps_per_launch = 3
@@ -273,7 +277,7 @@ def test_batch_steps_per_launch_defaults_and_arguments():
 
 
 @pytest.mark.parametrize("storage,spl", [(s, k) for s in ("fp32", "mixed", "fp16", "bf16") for k in (1, 2, 3, 4)]
-                         + [("fp64", 1), ("fp64", 2)])
+                         + [("fp32", 5), ("fp64", 1), ("fp64", 2)])
 def test_streaming_batch_members_equal_single_runs(storage, spl):
     """23 steps (launches of spl steps and single steps for the rest, spl
     changed once mid-run): every member equals its single-cavity run bit
@@ -286,7 +290,7 @@ def test_streaming_batch_members_equal_single_runs(storage, spl):
     b.steps_per_launch = spl
     b.init(seeds, amps)
     b.step(10)
-    b.steps_per_launch = {1: 4, 2: 3, 3: 4, 4: 3}[spl] if storage != "fp64" else 3 - spl
+    b.steps_per_launch = {1: 4, 2: 3, 3: 4, 4: 3, 5: 2}[spl] if storage != "fp64" else 3 - spl
     b.step(13)
     assert b.t == 23
     hot, cold = b.nusselt()
@@ -297,18 +301,20 @@ def test_streaming_batch_members_equal_single_runs(storage, spl):
     assert not b.unstable().any()
 
 
-@pytest.mark.parametrize("graph_steps", [4, 6])
-def test_streaming_graph_replay_matches_eager(graph_steps):
-    """Graphs of four-step launches plus single steps (6 = one launch of
-    four and two single steps, which leaves the buffers swapped), keyed by
-    the parity of t and the buffer; each replay checked against eager."""
+@pytest.mark.parametrize("spl,graph_steps", [(4, 4), (4, 6), (5, 10), (5, 12)])
+def test_streaming_graph_replay_matches_eager(spl, graph_steps):
+    """Graphs of multi-step launches plus single steps (6 = one launch of
+    four and two single steps, which leaves the buffers swapped; 12 = two of
+    five and two single steps), keyed by the parity of t and the buffer;
+    each replay checked against eager."""
     import torch
     cfgs = _small_batch("fp32", 2)
     seeds = list(range(len(cfgs)))
     amps = [1e-2] * len(cfgs)
     eager = lbm.Batch(cfgs)
     graph = lbm.Batch(cfgs)
-    assert eager.steps_per_launch == graph.steps_per_launch == 4
+    assert eager.steps_per_launch == graph.steps_per_launch == 5
+    eager.steps_per_launch = graph.steps_per_launch = spl
     graph.set_config(block=256, grid_per_cu=0, graph_steps=graph_steps)
     eager.init(seeds, amps)
     graph.init(seeds, amps)

@@ -47,13 +47,14 @@ def _run(cfg, spl, steps, seed=9, amp=2e-2):
 @pytest.mark.parametrize("shape", SHAPES)
 def test_multi_step_bitwise(storage, shape):
     """23 steps: 11 launches of two + one single step, 7 of three + one of
-    two, 5 of four + one of three, against 23 single steps (FP64: two)."""
+    two, 5 of four + one of three, 4 of five + one of three (FP32), against
+    23 single steps (FP64: two)."""
     for name, cfg in _layouts(shape, storage).items():
         if name != "box" and min(shape) < 2:
             continue  # a walled axis needs two nodes
         one = _run(cfg, 1, 23)
         a = one.export_state()
-        for spl in (2, 3, 4) if storage != "fp64" else (2,):  # FP64: two steps at most
+        for spl in {"fp64": (2,), "fp32": (2, 3, 4, 5)}.get(storage, (2, 3, 4)):
             other = _run(cfg, spl, 23)
             assert one.t == other.t == 23
             b = other.export_state()
@@ -103,7 +104,7 @@ def test_two_step_after_single_steps_and_nusselt():
     cfg = W.rayleigh_benard(2, (257, 129), ra=1e5, pr=0.71, storage="fp32")
     ref = _run(cfg, 1, 0)
     mix = _run(cfg, 1, 0)
-    for n, spl in ((3, 2), (4, 1), (1, 3), (6, 3), (5, 2), (7, 4), (9, 3), (4, 4)):
+    for n, spl in ((3, 2), (4, 1), (1, 3), (6, 3), (5, 2), (7, 4), (9, 3), (4, 4), (11, 5), (5, 5), (3, 5)):
         ref.step(n)
         mix.steps_per_launch = spl
         mix.step(n)
@@ -112,21 +113,26 @@ def test_two_step_after_single_steps_and_nusselt():
 
 
 def test_steps_per_launch_arguments():
-    defaults = {"fp32": 4, "mixed": 4, "fp16": 3, "bf16": 3, "fp64": 2}
+    defaults = {"fp32": 5, "mixed": 4, "fp16": 3, "bf16": 4, "fp64": 2}
     for st, k in defaults.items():
         assert lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage=st)).steps_per_launch == k
     c2 = lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage="fp32"))
-    for bad in (0, 5, -1):
+    for bad in (0, 6, -1):
         with pytest.raises(lbm.LBMError) as e:
             c2.steps_per_launch = bad
         assert e.value.status == -1
+    for st in ("fp16", "bf16", "mixed"):  # five steps: FP32 storage only
+        c16 = lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage=st))
+        with pytest.raises(lbm.LBMError) as e:
+            c16.steps_per_launch = 5
+        assert e.value.status == -5
     c64 = lbm.Cavity(W.rayleigh_benard(2, (33, 17), ra=1e4, pr=0.71, storage="fp64"))
-    for k in (3, 4):
+    for k in (3, 4, 5):
         with pytest.raises(lbm.LBMError) as e:
             c64.steps_per_launch = k
         assert e.value.status == -5
     c3 = lbm.Cavity(W.rayleigh_benard(3, (9, 9, 9), ra=1e4, pr=0.71, storage="fp32"))
-    for k in (3, 4):
+    for k in (3, 4, 5):
         with pytest.raises(lbm.LBMError) as e:
             c3.steps_per_launch = k
         assert e.value.status == -5
@@ -151,8 +157,8 @@ BIG = [("fp64", (8193, 8193)), ("fp32", (12289, 12289)), ("mixed", (14849, 14849
 @pytest.mark.parametrize("storage,shape", BIG)
 def test_multi_step_beyond_4gib_arrays(storage, shape):
     """Moments and wall fluxes agree bitwise after 7 steps with one step per
-    launch and with the storage mode's default (7 = 4 + 3, 3 + 3 + 1 or
-    2 + 2 + 2 + 1 steps per launch)."""
+    launch and with the storage mode's default (7 = 5 + 2, 4 + 3, 3 + 3 + 1
+    or 2 + 2 + 2 + 1 steps per launch)."""
     import torch
     cfg = W.rayleigh_benard(2, shape, ra=1e8, pr=0.71, storage=storage)
     N = shape[0] * shape[1]
@@ -161,7 +167,7 @@ def test_multi_step_beyond_4gib_arrays(storage, shape):
     eg = {"fp64": 8, "fp32": 4, "mixed": 4, "fp16": 2, "bf16": 2}[storage]
     assert max(N * qf * ef, N * qg * eg) > 2 ** 32  # the 64-bit path
     res = []
-    for spl in (1, {"fp64": 2, "fp32": 4, "mixed": 4, "fp16": 3, "bf16": 3}[storage]):
+    for spl in (1, {"fp64": 2, "fp32": 5, "mixed": 4, "fp16": 3, "bf16": 4}[storage]):
         print(f"{storage} {shape}: {spl} steps per launch", flush=True)
         c = _run(cfg, spl, 7, amp=1e-3)
         rho = torch.empty(N, dtype=torch.float64, device="cuda")

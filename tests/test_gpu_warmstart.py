@@ -13,7 +13,7 @@ def test_warm_start_saves_steps_in_the_steady_regime():
     from paper_2211_03160_amd import warmstart as WS
     out = WS.run(**WS.QUICK)
     res = out["eval"]
-    print({k: v for k, v in out.items() if k not in ("eval", "loss_history")}, flush=True)
+    print({k: v for k, v in out.items() if k not in ("eval", "loss_history", "nu_history")}, flush=True)
     for r in res:
         print(r, flush=True)
     assert out["unstable_eval_runs"] == 0
