@@ -21,7 +21,7 @@ interpolated back to the full grid.  Large-scale rolls come in two mirror
 images; snapshots are mirrored to a clockwise mean circulation so the
 network learns one of them.
 
-Usage: python -m paper_2211_03160_amd.warmstart [--quick] [--out PATH]
+Usage: python -m paper_2211_03160_amd.warmstart [--quick] [--out PATH] [--profile-train STEPS]
 """
 from __future__ import annotations
 
@@ -363,6 +363,50 @@ def summarize(res, horizon, seed):
     return out
 
 
+def profile_train(steps=40, H=257, chans=(32, 64, 128, 256), batch=16, seed=7):
+    """Time `steps` training steps of the network at the shape of the 257^2
+    configuration (random BF16 inputs and targets), with HIP events, and
+    count the algorithmic FLOPs of its 3x3 convolutions (forward, data
+    gradient except for the first layer, weight gradient; 2 per
+    multiply-add).  Returns ms per step and TFLOP/s."""
+    import torch
+    levels = len(chans)
+    cfg = W.rayleigh_benard(2, (H, H), ra=1e6, pr=1.0)
+    _, _, hp, wp = coarse_shape(cfg, levels)
+    rng = np.random.default_rng(seed)
+    X = nn.to_bf16(torch.from_numpy(rng.standard_normal((batch, hp, wp, CIN)).astype(np.float32)).cuda())
+    Y = torch.from_numpy(rng.standard_normal((batch, hp, wp, 3)).astype(np.float32)).cuda()
+    M = torch.ones_like(Y)
+    net = nn.UNet(cin=CIN, cout=COUT, chans=chans, seed=seed)
+
+    def one():
+        y, tape = net.forward(X)
+        loss, dy = nn.mse(y, Y, M)
+        net.backward(tape, dy)
+        net.adam(lr=1e-4)
+
+    for _ in range(3):
+        one()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        one()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # layer resolutions: two per encoder level, two per decoder level, the
+    # output layer at full resolution
+    res = [lvl for lvl in range(levels) for _ in range(2)] + \
+          [lvl for lvl in range(levels - 2, -1, -1) for _ in range(2)] + [0]
+    flops = 0.0
+    for k, (lay, lvl) in enumerate(zip(net.layers, res)):
+        mac = batch * (hp >> lvl) * (wp >> lvl) * 9 * lay["ci"] * lay["co"]
+        flops += 2 * mac * (3 if k > 0 else 2)
+    return {"ms_per_step": ms, "gflop_per_step": flops / 1e9, "tflops": flops / (ms * 1e-3) / 1e12,
+            "batch": batch, "grid": [hp, wp], "chans": list(chans)}
+
+
 QUICK = dict(H=65, n_train=64, n_eval=8, steps=40000, snap_from=16000, snap_every=2000,
              chans=(32, 64), epochs=20, batch=16, ra_range=(1e4, 1e5), eval_steps=80000,
              eval_every=200, window=16)
@@ -372,9 +416,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--profile-train", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS training steps of the network at the 257^2 shape")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
+    if a.profile_train:
+        print(json.dumps(profile_train(a.profile_train)), flush=True)
+        return
     if a.quick:
         out = run(**QUICK)
     else:
