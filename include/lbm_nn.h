@@ -43,9 +43,9 @@ lbm_status lbm_nn_conv3x3_flip(const uint16_t* wt, int32_t cin, int32_t cout, ui
 
 /* Weight and bias gradients of a convolution with input x [n,h,w,cin] and
  * output gradient dz [n,h,w,cout]: dw [9][cout][cin] and db [cout] (FP32;
- * db may be NULL).  `partial` is scratch of chunks * 9 * cout * cin
- * floats; pixels are split into `chunks` ranges summed in order, so the
- * result does not depend on scheduling.                                 */
+ * db may be NULL; with db, cout <= 256).  `partial` is scratch of
+ * chunks * 9 * cout * cin floats; pixels are split into `chunks` ranges
+ * summed in order, so the result does not depend on scheduling.         */
 lbm_status lbm_nn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n, int32_t h,
                                 int32_t w, int32_t cin, int32_t cout, float* partial,
                                 int32_t chunks, float* dw, float* db, void* stream);

@@ -2,6 +2,9 @@
 // the BF16 MFMA network kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -51,12 +54,27 @@ lbm_status lbm_nn_conv3x3(const uint16_t* x, int32_t n, int32_t h, int32_t w, in
     if (P * (cin > cout ? cin : cout) > 4.0e9) return nn_fail(LBM_E_INVALID, "conv3x3: tensor too large");
     ConvArgs a{x, wt, bias, y, n, h, w, cin, cout, relu, (uint32_t)P, (uint32_t)((P + 15) / 16)};
     const int NT = cout % 64 == 0 ? 4 : cout % 32 == 0 ? 2 : 1;
-    const size_t waves = (size_t)a.ptiles * (cout / (16 * NT));
+    // pixel tiles per wavefront: as many as keep at least 4096 wavefronts
+    // (16 per compute unit) in the launch
+    const size_t waves1 = (size_t)a.ptiles * (cout / (16 * NT));
+    const int MT = waves1 >= 4 * 4096 ? 4 : waves1 >= 2 * 4096 ? 2 : 1;
+    const size_t waves = ((size_t)a.ptiles + MT - 1) / MT * (cout / (16 * NT));
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
     hipStream_t s = (hipStream_t)stream;
-    if (NT == 4) hipLaunchKernelGGL(conv3x3_kernel<4>, grid, block, 0, s, a);
-    else if (NT == 2) hipLaunchKernelGGL(conv3x3_kernel<2>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(conv3x3_kernel<1>, grid, block, 0, s, a);
+    auto go = [&](auto ntc, auto mtc) {
+        hipLaunchKernelGGL((conv3x3_kernel<decltype(ntc)::value, decltype(mtc)::value>), grid, block, 0, s, a);
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    auto by_mt = [&](auto ntc) {
+        if (MT == 4) go(ntc, I4{});
+        else if (MT == 2) go(ntc, I2{});
+        else go(ntc, I1{});
+    };
+    if (NT == 4) by_mt(I4{});
+    else if (NT == 2) by_mt(I2{});
+    else by_mt(I1{});
     return launched("conv3x3");
 }
 
@@ -88,8 +106,17 @@ lbm_status lbm_nn_conv3x3_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n
     hipLaunchKernelGGL(sum_chunks_kernel, dim3(grid1(count)), dim3(256), 0, s, (const float*)partial, used, count, dw);
     if ((st = launched("conv3x3_wgrad sum"))) return st;
     if (db) {
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(256), 0, s, dz, P, cout, db);
+        // the partial buffer is free again (stream order): bias sums of the
+        // same pixel chunks, then added in chunk order
+        // ranges of about 512 pixels (enough blocks to fill the GPU), at most
+        // as many partial sums as the scratch holds (9 cin >= 144 per chunk)
+        if (cout > 256) return nn_fail(LBM_E_INVALID, "conv3x3_wgrad: bias gradient needs cout <= 256");
+        const uint32_t nb_want = std::min<uint32_t>((P + 511) / 512, 144u * used);
+        const uint32_t per_b = (P + nb_want - 1) / nb_want, nb = (P + per_b - 1) / per_b;
+        hipLaunchKernelGGL(bias_partial_kernel, dim3(nb), dim3(256), 0, s, dz, P, cout, per_b, partial);
         if ((st = launched("conv3x3_wgrad bias"))) return st;
+        hipLaunchKernelGGL(bias_sum_kernel, dim3((unsigned)cout), dim3(256), 0, s, (const float*)partial, nb, cout, db);
+        if ((st = launched("conv3x3_wgrad bias sum"))) return st;
     }
     return LBM_OK;
 }

@@ -47,40 +47,56 @@ struct ConvArgs {
     uint32_t P, ptiles;  // pixels, 16-pixel tiles
 };
 
-// One wavefront computes 16 pixels x (16 NT) output channels.
-template <int NT>
+// One wavefront computes 16 MT pixels x (16 NT) output channels: each K
+// step loads MT activation fragments and NT weight fragments and issues
+// MT x NT MFMAs (the weight fragments are shared by the MT pixel tiles).
+template <int NT, int MT = 1>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t gw = blockIdx.x * 4 + (threadIdx.x >> 6);
     const uint32_t groups = (uint32_t)a.cout / (16 * NT);
-    if (gw >= a.ptiles * groups) return;
-    const uint32_t pt = gw % a.ptiles, cg = gw / a.ptiles;
+    const uint32_t pgroups = (a.ptiles + MT - 1) / MT;
+    if (gw >= pgroups * groups) return;
+    const uint32_t pg = gw % pgroups, cg = gw / pgroups;
     const uint32_t m = lane & 15, kg = lane >> 4;
-    const uint32_t p = pt * 16 + m;
-    const bool pin = p < a.P;
-    const int32_t pj = pin ? (int32_t)(p % a.w) : 0;
-    const int32_t pi = pin ? (int32_t)((p / a.w) % a.h) : 0;
-    const int32_t pn = pin ? (int32_t)(p / ((uint32_t)a.w * a.h)) : 0;
-    v4f acc[NT];
+    bool pin[MT];
+    int32_t pj[MT], pi[MT], pn[MT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < MT; ++u) {
+        const uint32_t p = (pg * MT + u) * 16 + m;
+        pin[u] = p < a.P;
+        pj[u] = pin[u] ? (int32_t)(p % a.w) : 0;
+        pi[u] = pin[u] ? (int32_t)((p / a.w) % a.h) : 0;
+        pn[u] = pin[u] ? (int32_t)(p / ((uint32_t)a.w * a.h)) : 0;
+    }
+    v4f acc[MT][NT];
+#pragma unroll
+    for (int u = 0; u < MT; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[u][t] = v4f{0.f, 0.f, 0.f, 0.f};
     const uint32_t K = 9u * (uint32_t)a.cin;
     for (uint32_t k0 = 0; k0 < K; k0 += 32) {
         // this lane's eight K values: tap, first input channel
         const uint32_t k = k0 + 8 * kg;
         const bool kin = k < K;
         const uint32_t tap = kin ? k / (uint32_t)a.cin : 0, ci0 = kin ? k % (uint32_t)a.cin : 0;
-        const int32_t si = pi + (int32_t)tap / 3 - 1, sj = pj + (int32_t)tap % 3 - 1;
-        const bool ok = kin && pin && si >= 0 && si < a.h && sj >= 0 && sj < a.w;
-        v4u av = v4u{0u, 0u, 0u, 0u};
-        if (ok) av = *(const v4u*)(a.x + ((size_t)((size_t)pn * a.h + si) * a.w + sj) * a.cin + ci0);
+        const int32_t dy = (int32_t)tap / 3 - 1, dx = (int32_t)tap % 3 - 1;
+        v4u av[MT];
+#pragma unroll
+        for (int u = 0; u < MT; ++u) {
+            const int32_t si = pi[u] + dy, sj = pj[u] + dx;
+            const bool ok = kin && pin[u] && si >= 0 && si < a.h && sj >= 0 && sj < a.w;
+            av[u] = v4u{0u, 0u, 0u, 0u};
+            if (ok) av[u] = *(const v4u*)(a.x + ((size_t)((size_t)pn[u] * a.h + si) * a.w + sj) * a.cin + ci0);
+        }
         const uint16_t* wtap = a.wt + (size_t)tap * a.cout * a.cin + ci0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const uint32_t co = (cg * NT + t) * 16 + m;
             v4u bv = v4u{0u, 0u, 0u, 0u};
             if (kin) bv = *(const v4u*)(wtap + (size_t)co * a.cin);
-            acc[t] = mfma32(av, bv, acc[t]);
+#pragma unroll
+            for (int u = 0; u < MT; ++u) acc[u][t] = mfma32(av[u], bv, acc[u][t]);
         }
     }
 #pragma unroll
@@ -88,14 +104,16 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
         const uint32_t co = (cg * NT + t) * 16 + m;
         const float bb = a.bias ? a.bias[co] : 0.0f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t q = pt * 16 + 4 * kg + j;
-            if (q < a.P) {
-                float v = acc[t][j] + bb;
-                if (a.relu) v = fmaxf(v, 0.0f);
-                a.y[(size_t)q * a.cout + co] = f2bf(v);
+        for (int u = 0; u < MT; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t q = (pg * MT + u) * 16 + 4 * kg + j;
+                if (q < a.P) {
+                    float v = acc[u][t][j] + bb;
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    a.y[(size_t)q * a.cout + co] = f2bf(v);
+                }
             }
-        }
     }
 }
 
@@ -122,53 +140,74 @@ struct WGradArgs {
 
 // dW[tap][co][ci] = sum_p dz[p][co] x[p shifted by tap][ci]: M = co,
 // N = ci (4 tiles per wave), K = pixels of one chunk, 32 per instruction.
+// Both operands are stored pixel-major, so a lane's eight consecutive
+// pixels of one channel are 2 cout (2 cin) bytes apart: every K step loads
+// the 32-pixel tiles with 16-byte loads (8 channels of one pixel per lane)
+// and writes them transposed into the wavefront's own LDS area, from which
+// each operand fragment is one 16-byte read.  (A wavefront's LDS accesses
+// execute in order, so no barrier is needed: the wavefronts of a block
+// share nothing.)
+constexpr int kWgPad = 40;  // LDS row of 32 pixels plus 8 (spreads the banks of the fragment reads)
+struct WgradLds {
+    uint16_t a[16][kWgPad];  // dz tile, [co][pixel]
+    uint16_t b[64][kWgPad];  // x tile, [ci][pixel]
+};
 __global__ __launch_bounds__(256) void wgrad_kernel(WGradArgs a) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ WgradLds lds[4];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t gw = blockIdx.x * 4 + wv;
     // input channels in groups of up to four 16-wide tiles per wavefront
     const uint32_t cot = (uint32_t)a.cout / 16, cit = ((uint32_t)a.cin + 63) / 64;
     const uint32_t per_chunk = 9 * cot * cit;
-    if (gw >= per_chunk * a.chunks) return;
+    if (gw >= per_chunk * a.chunks) return;  // whole wavefront
+    WgradLds& L = lds[wv];
     const uint32_t chunk = gw / per_chunk, r = gw % per_chunk;
     const uint32_t tap = r / (cot * cit), cb = (r / cit) % cot, ib = r % cit;
     const int rest = a.cin / 16 - (int)ib * 4;
     const int NTc = rest < 4 ? rest : 4;
     const int32_t di = (int32_t)tap / 3 - 1, dj = (int32_t)tap % 3 - 1;
     const uint32_t m = lane & 15, kg = lane >> 4;
+    // this lane's share of the tile loads: pixel pl of the step, channels ch8 .. ch8 + 7
+    const uint32_t pl = lane >> 1, ch8 = (lane & 1) * 8;
     v4f acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
     const uint32_t p_begin = chunk * a.chunk;
     const uint32_t p_end = p_begin + a.chunk < a.P ? p_begin + a.chunk : a.P;
     for (uint32_t p0 = p_begin; p0 < p_end; p0 += 32) {
-        // K = 32 pixels: this lane's eight are p0 + 8 kg + j
-        uint16_t av[8];
-        int32_t src[8];
+        const uint32_t p = p0 + pl;
+        v4u dv = v4u{0u, 0u, 0u, 0u};
+        v4u xv[4] = {v4u{0u, 0u, 0u, 0u}, v4u{0u, 0u, 0u, 0u}, v4u{0u, 0u, 0u, 0u}, v4u{0u, 0u, 0u, 0u}};
+        if (p < p_end) {
+            dv = *(const v4u*)(a.dz + (size_t)p * a.cout + cb * 16 + ch8);
+            const int32_t pj = (int32_t)(p % a.w), pi = (int32_t)((p / a.w) % a.h);
+            const int32_t pn = (int32_t)(p / ((uint32_t)a.w * a.h));
+            const int32_t si = pi + di, sj = pj + dj;
+            if (si >= 0 && si < a.h && sj >= 0 && sj < a.w) {
+                const uint16_t* xs = a.x + (size_t)((pn * a.h + si) * a.w + sj) * a.cin + ib * 64 + ch8;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint32_t p = p0 + 8 * kg + j;
-            uint16_t v = 0;
-            src[j] = -1;
-            if (p < p_end) {
-                v = a.dz[(size_t)p * a.cout + cb * 16 + m];
-                const int32_t pj = (int32_t)(p % a.w), pi = (int32_t)((p / a.w) % a.h);
-                const int32_t pn = (int32_t)(p / ((uint32_t)a.w * a.h));
-                const int32_t si = pi + di, sj = pj + dj;
-                if (si >= 0 && si < a.h && sj >= 0 && sj < a.w) src[j] = (pn * a.h + si) * a.w + sj;
+                for (int t = 0; t < 4; ++t)
+                    if (t < NTc) xv[t] = *(const v4u*)(xs + t * 16);
             }
-            av[j] = v;
         }
-        const v4u a8 = __builtin_bit_cast(v4u, av);
+        // transposed into LDS: channel-major rows of 32 pixels
+        {
+            const uint16_t* d = (const uint16_t*)&dv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) L.a[ch8 + j][pl] = d[j];
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (t < NTc) {
-                uint16_t bv[8];
+                const uint16_t* xx = (const uint16_t*)&xv[t];
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    bv[j] = src[j] >= 0 ? a.x[(size_t)src[j] * a.cin + (ib * 4 + t) * 16 + m] : (uint16_t)0;
-                acc[t] = mfma32(a8, __builtin_bit_cast(v4u, bv), acc[t]);
+                for (int j = 0; j < 8; ++j) L.b[t * 16 + ch8 + j][pl] = xx[j];
             }
         }
+        const v4u a8 = *(const v4u*)&L.a[m][8 * kg];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (t < NTc) acc[t] = mfma32(a8, *(const v4u*)&L.b[t * 16 + m][8 * kg], acc[t]);
     }
     float* out = a.partial + ((size_t)chunk * 9 + tap) * a.cout * a.cin;
 #pragma unroll
@@ -193,19 +232,54 @@ __global__ void sum_chunks_kernel(const float* partial, uint32_t chunks, size_t 
     }
 }
 
-// db[co] = sum_p dz[p][co]: one block per channel, fixed reduction order
-__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t* dz, uint32_t P, int32_t cout, float* db) {
-    __shared__ float lds[256];
-    const int32_t co = blockIdx.x;
-    float s = 0.0f;
-    for (uint32_t p = threadIdx.x; p < P; p += 256) s += bf2f(dz[(size_t)p * cout + co]);
-    lds[threadIdx.x] = s;
+// db[co] = sum_p dz[p][co] in two passes with a fixed reduction order.
+// Pass 1: block c sums pixels [c per, (c + 1) per) of every channel into
+// partial[c][co]: thread t takes channels 8 (t % G) .. + 7 (G = cout / 8
+// groups, one 16-byte load) of every R-th pixel (R = 256 / G rows side by
+// side, so a row is one contiguous read), then the R row sums are added in
+// order.  Pass 2 is bias_sum_kernel over the blocks.
+__global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t* dz, uint32_t P, int32_t cout,
+                                                           uint32_t per, float* partial) {
+    __shared__ float lds[256 * 8];
+    const uint32_t G = (uint32_t)cout / 8, R = 256u / G;
+    const uint32_t t = threadIdx.x, grp = t % G, row = t / G;
+    const uint32_t p0 = blockIdx.x * per, p1 = p0 + per < P ? p0 + per : P;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (row < R) {
+        for (uint32_t p = p0 + row; p < p1; p += R) {
+            const v4u v = *(const v4u*)(dz + (size_t)p * cout + grp * 8);
+            const uint16_t* h = (const uint16_t*)&v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j] += bf2f(h[j]);
+        }
+    }
+    if (row < R) {  // (256 % G threads beyond the last row hold nothing)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds[row * (uint32_t)cout + grp * 8 + j] = s[j];
+    }
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+    if (t < (uint32_t)cout) {
+        float v = 0.0f;
+        for (uint32_t k = 0; k < R; ++k) v += lds[k * (uint32_t)cout + t];
+        partial[(size_t)blockIdx.x * cout + t] = v;
+    }
+}
+
+// Pass 2 of the bias gradient: db[co] = sum over the nb partial sums of
+// channel co, one block per channel: thread t adds partials t, t + 256, ...
+// in order, then the 256 sums are added pairwise in a fixed tree.
+__global__ __launch_bounds__(256) void bias_sum_kernel(const float* partial, uint32_t nb, int32_t cout, float* db) {
+    __shared__ float lds[256];
+    const uint32_t co = blockIdx.x, t = threadIdx.x;
+    float s = 0.0f;
+    for (uint32_t b = t; b < nb; b += 256) s += partial[(size_t)b * cout + co];
+    lds[t] = s;
+    __syncthreads();
+    for (uint32_t o = 128; o > 0; o >>= 1) {
+        if (t < o) lds[t] += lds[t + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) db[co] = lds[0];
+    if (t == 0) db[co] = lds[0];
 }
 
 __global__ void relu_backward_kernel(const uint16_t* y, const uint16_t* dy, uint16_t* dz, size_t count) {

@@ -57,7 +57,8 @@ def test_conv3x3_forward(n, h, w, ci, co, relu):
     assert np.all(err <= BF * np.abs(ref) + 1e-5 * scale), err.max()
 
 
-@pytest.mark.parametrize("n,h,w,ci,co", [(2, 6, 5, 16, 32), (1, 12, 12, 96, 32), (2, 8, 8, 64, 16)])
+@pytest.mark.parametrize("n,h,w,ci,co", [(2, 6, 5, 16, 32), (1, 12, 12, 96, 32), (2, 8, 8, 64, 16),
+                                         (4, 40, 40, 48, 48), (1, 20, 30, 32, 256)])
 def test_conv3x3_gradients(n, h, w, ci, co):
     import torch
     from paper_2211_03160_amd import nn
