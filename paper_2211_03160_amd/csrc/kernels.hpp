@@ -130,10 +130,11 @@ struct Geometry {
 };
 
 // Relaxation rates are indexed by row kind (RowKind), not by row: rows of
-// one kind share a rate, so a kernel holds only the distinct values.  Where
-// every kind's rows also share |M_k|^2 (2D), s, b and q come divided by it,
+// one kind share a rate, so a kernel holds only the distinct values.  In 2D
+// every kind's rows also share |M_k|^2, and s, b and q come divided by it,
 // which saves the scaling of each relaxed moment before the inverse
-// transform (folded_rates).
+// transform.  In 3D two kinds have rows of different norms, and the
+// collision takes per-row factors instead (k3, below).
 // Temperature of the thermal reference state at a node: T_b = tb0 + tbg k
 // with k the node's coordinate along `axis` (tbg = 0 where the reference is
 // the uniform T0).
@@ -146,6 +147,15 @@ __host__ __device__ __forceinline__ R base_temp(const BaseTemp<R>& b, uint32_t x
     const uint32_t k = b.axis == 0 ? x : b.axis == 1 ? y : z;
     return b.tb0 + b.tbg * (R)k;
 }
+
+// entries of Coef::k3: S* multiply a row's non-equilibrium part, B* its
+// forcing term; flow rows e, eps, q, 3p_xx, 3pi_xx, p_ww, pi_ww, the three
+// off-diagonal stresses (O), the third-order rows m; heat rows j, e, 3p_xx,
+// p_ww
+enum K3 : int {
+    k3SE, k3BE, k3SEps, k3BEps, k3SQ, k3BQ, k3SP, k3BP, k3SPi, k3BPi,
+    k3SW, k3BW, k3SWi, k3BWi, k3SO, k3BO, k3SM, k3QJ, k3QE, k3QP, k3QW, kK3Count
+};
 
 template <class R> struct Coef {
     R s[10];     // flow rate per row kind (0 on conserved kinds)
@@ -162,12 +172,14 @@ template <class R> struct Coef {
     // heat entering through one link of a face of the reference axis in the
     // reference state, FP64 (0 on the other faces)
     double flux_c[6];
+    // 3D only: each row's relaxation factor and forcing factor divided by
+    // |M_k|^2, with the integer factor its relaxed term carries in
+    // collide_store_d3 folded in (indices K3)
+    R k3[kK3Count];
 };
 
-template <int DIM> constexpr bool folded_rates() {
-    return kinds_share_norm<Flow<DIM>>() && kinds_share_norm<Heat<DIM>>();
-}
-static_assert(folded_rates<2>() && !folded_rates<3>(), "2D rates carry 1/|M_k|^2, 3D ones do not");
+static_assert(kinds_share_norm<Flow<2>>() && kinds_share_norm<Heat<2>>() && !kinds_share_norm<Flow<3>>(),
+              "2D rates carry 1/|M_k|^2, 3D ones do not");
 
 template <class St> struct StepArgs {
     const typename St::TF* fsrc;
@@ -201,82 +213,6 @@ template <int B, int E, class F> __device__ __forceinline__ void static_for(F&& 
     if constexpr (B < E) {
         f(std::integral_constant<int, B>{});
         static_for<B + 1, E>(f);
-    }
-}
-
-// acc += C v for a compile-time integer coefficient C
-template <int C, class R> __device__ __forceinline__ void cmac(R& acc, R v) {
-    if constexpr (C == 1) acc += v;
-    else if constexpr (C == -1) acc -= v;
-    else if constexpr (C != 0) acc += R(C) * v;
-}
-
-// m_eq(rho, u) - m_eq(1, 0) for the non-conserved rows (second-order
-// equilibrium with local rho)
-template <int DIM, class R>
-__device__ __forceinline__ R eq_dev(int k, R rho, R drho, const R* u) {
-    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    if constexpr (DIM == 2) {
-        switch (k) {
-        case 1: return R(-2) * drho + R(3) * rho * uu;
-        case 2: return drho - R(3) * rho * uu;
-        case 4: return -rho * u[0];
-        case 6: return -rho * u[1];
-        case 7: return rho * (u[0] * u[0] - u[1] * u[1]);
-        case 8: return rho * u[0] * u[1];
-        default: return R(0);
-        }
-    } else {
-        const R pxx = R(3) * u[0] * u[0] - uu, pww = u[1] * u[1] - u[2] * u[2];
-        switch (k) {
-        case 1: return R(-11) * drho + R(19) * rho * uu;
-        case 2: return R(3) * drho - R(5.5) * rho * uu;
-        case 4: return R(-2.0 / 3.0) * rho * u[0];
-        case 6: return R(-2.0 / 3.0) * rho * u[1];
-        case 8: return R(-2.0 / 3.0) * rho * u[2];
-        case 9: return rho * pxx;
-        case 10: return R(-0.5) * rho * pxx;
-        case 11: return rho * pww;
-        case 12: return R(-0.5) * rho * pww;
-        case 13: return rho * u[0] * u[1];
-        case 14: return rho * u[1] * u[2];
-        case 15: return rho * u[0] * u[2];
-        default: return R(0);
-        }
-    }
-}
-
-// forcing moments M F~ of Eq. (6a) / Eq. (6b); the xy entry of Eq. (6a)
-// is u F_y + v F_x
-template <int DIM, class R>
-__device__ __forceinline__ R force_mom(int k, const R* u, const R* F) {
-    const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-    if constexpr (DIM == 2) {
-        switch (k) {
-        case 1: return R(6) * uF;
-        case 2: return R(-6) * uF;
-        case 4: return -F[0];
-        case 6: return -F[1];
-        case 7: return R(2) * u[0] * F[0] - R(2) * u[1] * F[1];
-        case 8: return u[0] * F[1] + u[1] * F[0];
-        default: return R(0);
-        }
-    } else {
-        switch (k) {
-        case 1: return R(38) * uF;
-        case 2: return R(-11) * uF;
-        case 4: return R(-2.0 / 3.0) * F[0];
-        case 6: return R(-2.0 / 3.0) * F[1];
-        case 8: return R(-2.0 / 3.0) * F[2];
-        case 9: return R(4) * u[0] * F[0] - R(2) * u[1] * F[1] - R(2) * u[2] * F[2];
-        case 10: return R(-2) * u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-        case 11: return R(2) * u[1] * F[1] - R(2) * u[2] * F[2];
-        case 12: return -u[1] * F[1] + u[2] * F[2];
-        case 13: return u[0] * F[1] + u[1] * F[0];
-        case 14: return u[1] * F[2] + u[2] * F[1];
-        case 15: return u[0] * F[2] + u[2] * F[0];
-        default: return R(0);
-        }
     }
 }
 
@@ -344,13 +280,14 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// The 2D collision (D2Q9 flow, D2Q5 heat) written out: the same moments,
-// equilibria, forcing moments and inverse transforms as the generic form
-// below, with the terms that several rows share formed once.  Velocities:
-// 1 +x, 2 +y, 3 -x, 4 -y, 5 (+x,+y), 6 (-x,+y), 7 (-x,-y), 8 (+x,-y); flow
-// rows rho, e, eps, jx, qx, jy, qy, pxx, pxy; heat rows T, jx, jy, e, pxx.
-// Rates come divided by their rows' |M_k|^2 (folded_rates).  Buoyancy acts
-// along y only, so every F_x term is dropped.
+// The 2D collision (D2Q9 flow, D2Q5 heat) written out: the moments of the
+// basis in lattice.hpp, their second-order equilibria (m_eq(rho, u) -
+// m_eq(1, 0) in deviation form), the Guo forcing moments of Eq. (6a) and
+// the inverse transform, with the terms that several rows share formed
+// once.  Velocities: 1 +x, 2 +y, 3 -x, 4 -y, 5 (+x,+y), 6 (-x,+y), 7
+// (-x,-y), 8 (+x,-y); flow rows rho, e, eps, jx, qx, jy, qy, pxx, pxy;
+// heat rows T, jx, jy, e, pxx.  Rates come divided by their rows' |M_k|^2.
+// Buoyancy acts along y only, so every F_x term is dropped.
 template <class St, class Dst>
 __device__ __forceinline__ bool collide_store_d2(typename St::R* h, typename St::R* g,
                                                  const Coef<typename St::R>& c, typename St::R tb,
@@ -441,172 +378,177 @@ __device__ __forceinline__ bool collide_store_d2(typename St::R* h, typename St:
     return isfinite(drho + dT) && ux2 + uy2 <= R(1.0 / 3.0);
 }
 
-// The collision for any basis with opposite pairs (used in 3D).
-template <int DIM, class St, class Dst>
-__device__ __forceinline__ bool collide_store_nd(typename St::R* hf, typename St::R* hg,
-                                              const Coef<typename St::R>& c, typename St::R tb, const Dst& dst) {
+// The 3D collision (D3Q19 flow, D3Q7 heat) written out: the moments of
+// the basis in lattice.hpp (rows rho, e, eps, jx, qx, jy, qy, jz, qz,
+// 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z; heat rows
+// T, jx, jy, jz, e, 3p_xx, p_ww), their equilibria and Guo forcing moments
+// (Eq. 6b) with buoyancy along z only, and the inverse transform, with the
+// terms that several rows share formed once.  Velocities: 1/2 +-x, 3/4
+// +-y, 5/6 +-z, then the edge pairs 7/8 (1,1,0), 9/10 (1,-1,0), 11/12
+// (1,0,1), 13/14 (1,0,-1), 15/16 (0,1,1), 17/18 (0,1,-1).  Each relaxed
+// increment dm_k = d_k / |M_k|^2 uses the factors of Coef::k3, and the
+// equilibrium parts use rho u = J = j + F/2: rho u_a u_b = J_a u_b.
+template <class St, class Dst>
+__device__ __forceinline__ bool collide_store_d3(typename St::R* h, typename St::R* g,
+                                                 const Coef<typename St::R>& c, typename St::R tb,
+                                                 const Dst& dst) {
     using R = typename St::R;
-    using L = Flow<DIM>;
-    using H = Heat<DIM>;
-    constexpr int QF = L::Q, QG = H::Q;
-
-    // Opposite velocities pair up (i, opp i); every moment row is even
-    // (M_k,opp i = M_k,i) or odd (M_k,opp i = -M_k,i, M_k,0 = 0), so even
-    // rows are sums over the pair sums S and odd rows over the pair
-    // differences D, and the inverse transform gives each pair an even part
-    // e and an odd part o: h_i += e + o, h_opp i += e - o.
-    R S[QF], D[QF];  // at pair heads
-    static_for<1, QF>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if constexpr (pair_head<L>(i)) {
-            S[i] = hf[i] + hf[L::opp[i]];
-            D[i] = hf[i] - hf[L::opp[i]];
-        }
-    });
-    auto flow_moment = [&](auto kc) -> R {
-        constexpr int k = decltype(kc)::value;
-        constexpr int par = row_parity<L>(k);
-        R mk = R(0);
-        if constexpr (par > 0) cmac<L::M(k, 0)>(mk, hf[0]);
-        static_for<1, QF>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            if constexpr (pair_head<L>(i)) cmac<L::M(k, i)>(mk, par > 0 ? S[i] : D[i]);
-        });
-        return mk;
-    };
-    const R drho = flow_moment(std::integral_constant<int, 0>{});
-    R j[3] = {R(0), R(0), R(0)};
-    static_for<1, QF>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if constexpr (pair_head<L>(i)) {
-            cmac<L::ex[i]>(j[0], D[i]);
-            cmac<L::ey[i]>(j[1], D[i]);
-            cmac<L::ez[i]>(j[2], D[i]);
-        }
-    });
-    R Sg[QG], Dg[QG];
-    static_for<1, QG>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if constexpr (pair_head<H>(i)) {
-            Sg[i] = hg[i] + hg[H::opp[i]];
-            Dg[i] = hg[i] - hg[H::opp[i]];
-        }
-    });
-    auto heat_moment = [&](auto kc) -> R {
-        constexpr int k = decltype(kc)::value;
-        constexpr int par = row_parity<H>(k);
-        R nk = R(0);
-        if constexpr (par > 0) cmac<H::M(k, 0)>(nk, hg[0]);
-        static_for<1, QG>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            if constexpr (pair_head<H>(i)) cmac<H::M(k, i)>(nk, par > 0 ? Sg[i] : Dg[i]);
-        });
-        return nk;
-    };
-    const R dT = heat_moment(std::integral_constant<int, 0>{});
+    const R* k = c.k3;
+    // flow moments from the sums S and differences D of opposite pairs
+    const R Sx = h[1] + h[2], Dx = h[1] - h[2];
+    const R Sy = h[3] + h[4], Dy = h[3] - h[4];
+    const R Sz = h[5] + h[6], Dz = h[5] - h[6];
+    const R S7 = h[7] + h[8], D7 = h[7] - h[8];
+    const R S9 = h[9] + h[10], D9 = h[9] - h[10];
+    const R S11 = h[11] + h[12], D11 = h[11] - h[12];
+    const R S13 = h[13] + h[14], D13 = h[13] - h[14];
+    const R S15 = h[15] + h[16], D15 = h[15] - h[16];
+    const R S17 = h[17] + h[18], D17 = h[17] - h[18];
+    const R Syz = Sy + Sz, A = Sx + Syz;                   // axis sum
+    const R Exy = S7 + S9, Exz = S11 + S13, Eyz = S15 + S17;  // edge sums per plane
+    const R Exyz = Exy + Exz, B = Exyz + Eyz;              // edge sum
+    const R drho = (h[0] + A) + B;
+    // 3p_xx, 3pi_xx = (Pa + Pe, -2 Pa + Pe); p_ww, pi_ww = (Wa + We, -2 Wa + We)
+    const R Pa = fmar(R(2), Sx, -Syz), Pe = fmar(R(-2), Eyz, Exyz);
+    const R Wa = Sy - Sz, We = Exy - Exz;
+    const R m_p = Pa + Pe, m_pi = fmar(R(-2), Pa, Pe);
+    const R m_w = Wa + We, m_wi = fmar(R(-2), Wa, We);
+    const R m_xy = S7 - S9, m_xz = S11 - S13, m_yz = S15 - S17;
+    // odd rows: j_a = D_a + E_a and q_a = -4 D_a + E_a per axis, E_a the
+    // edge part; m from the same pair combinations
+    const R a7 = D7 + D9, b7 = D7 - D9, a11 = D11 + D13, b11 = D11 - D13, a15 = D15 + D17, b15 = D15 - D17;
+    const R Ex = a7 + a11, Ey = b7 + a15, Ez = b11 + b15;
+    const R jx = Dx + Ex, jy = Dy + Ey, jz = Dz + Ez;
+    const R m_x = a7 - a11, m_y = a15 - b7, m_z = b11 - b15;
+    // heat moments
+    const R Sgx = g[1] + g[2], Dgx = g[1] - g[2];
+    const R Sgy = g[3] + g[4], Dgy = g[3] - g[4];
+    const R Sgz = g[5] + g[6], Dgz = g[5] - g[6];
+    const R Sgyz = Sgy + Sgz, Cg = Sgx + Sgyz;
+    const R dT = g[0] + Cg;
+    const R n_e = fmar(R(-6), g[0], Cg);
+    const R n_p = fmar(R(2), Sgx, -Sgyz), n_w = Sgy - Sgz;
+    // macroscopic fields, the buoyancy force F = (0, 0, Fz), u = J / rho
     const R rho = R(1) + drho;
     const R T = tb + dT;
-    R F[3] = {R(0), R(0), R(0)};
-    F[DIM - 1] = rho * c.gbeta * (dT + (tb - c.t0));  // buoyancy, upward
+    const R Fz = rho * c.gbeta * (dT + (tb - c.t0));
     const R inv_rho = recip(rho);
-    R u[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = (j[a] + R(0.5) * F[a]) * inv_rho;
-
-    // flow: dm_k for every row, scaled by 1/|M_k|^2
-    R dm[QF];
-    static_for<0, QF>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        constexpr int kind = L::kind[k];
-        R d;
-        if constexpr (kind == kRho) {
-            d = R(0);
-        } else if constexpr (kind == kJx || kind == kJy || kind == kJz) {
-            d = F[kind - kJx];  // momentum gains exactly F for any rate
-        } else {
-            const R mk = flow_moment(kc);
-            d = -c.s[kind] * (mk - eq_dev<DIM>(k, rho, drho, u)) + c.b[kind] * force_mom<DIM>(k, u, F);
-        }
-        // the rates of non-conserved rows already carry 1/|M_k|^2 when folded
-        constexpr bool scaled = folded_rates<DIM>() && kind != kRho && kind != kJx && kind != kJy && kind != kJz;
-        if constexpr (scaled) dm[k] = d;
-        else dm[k] = d * R(1.0 / row_norm<L>(k));
-    });
+    const R Jz = fmar(R(0.5), Fz, jz);
+    const R ux = jx * inv_rho, uy = jy * inv_rho, uz = Jz * inv_rho;
+    const R px = jx * ux, py = jy * uy, pz = Jz * uz;  // rho u_a^2
+    const R pyz = py + pz, ruu = px + pyz;             // rho |u|^2
+    const R pxx = fmar(R(2), px, -pyz), pww = py - pz;  // rho (3 ux^2 - |u|^2), rho (uy^2 - uz^2)
+    const R uF = uz * Fz;
+    // relaxed increments: -s (m - m_eq) + b (M F~) over |M_k|^2, where
+    // m_e - m_e,eq = 19 (B - h0 - rho |u|^2), m_eps - m_eps,eq = 9 h0 - 7 A
+    // - 2 B + 11/2 rho |u|^2, q_a - q_a,eq = 5/3 (E_a - 2 D_a) (+ Fz / 3 on
+    // z); (M F~) = 38 uF and -11 uF on e and eps, -2 uF on 3p_xx and p_ww,
+    // uF on 3pi_xx and pi_ww, -2/3 Fz on q_z, uy Fz and ux Fz on p_yz and
+    // p_xz; the momentum rows gain exactly F
+    const R dm_e = fmar(k[k3BE], uF, k[k3SE] * ((B - h[0]) - ruu));
+    const R dm_eps = fmar(k[k3BEps], uF, k[k3SEps] * fmar(R(5.5), ruu, fmar(R(9), h[0], -fmar(R(7), A, R(2) * B))));
+    const R dm_qx = k[k3SQ] * fmar(R(-2), Dx, Ex);
+    const R dm_qy = k[k3SQ] * fmar(R(-2), Dy, Ey);
+    const R dm_qz = fmar(k[k3BQ], Fz, k[k3SQ] * fmar(R(-2), Dz, Ez));
+    const R dm_jz = Fz * R(1.0 / row_norm<Flow<3>>(7));
+    const R dm_p = fmar(k[k3BP], uF, k[k3SP] * (m_p - pxx));
+    const R dm_pi = fmar(k[k3BPi], uF, k[k3SPi] * fmar(R(0.5), pxx, m_pi));
+    const R dm_w = fmar(k[k3BW], uF, k[k3SW] * (m_w - pww));
+    const R dm_wi = fmar(k[k3BWi], uF, k[k3SWi] * fmar(R(0.5), pww, m_wi));
+    const R dm_xy = k[k3SO] * fmar(-jx, uy, m_xy);
+    const R dm_yz = fmar(k[k3BO], uy * Fz, k[k3SO] * fmar(-jy, uz, m_yz));
+    const R dm_xz = fmar(k[k3BO], ux * Fz, k[k3SO] * fmar(-jx, uz, m_xz));
+    const R dm_mx = k[k3SM] * m_x, dm_my = k[k3SM] * m_y, dm_mz = k[k3SM] * m_z;
+    // inverse transform: h_i += sum_k M_ki dm_k, as even and odd parts of
+    // each opposite pair
+    h[0] = fmar(R(-30), dm_e, fmar(R(12), dm_eps, h[0]));
     {
-        R acc = hf[0];
-        static_for<1, QF>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            if constexpr (row_parity<L>(k) > 0) cmac<L::M(k, 0)>(acc, dm[k]);
-        });
-        hf[0] = acc;
+        const R C = fmar(R(-11), dm_e, R(-4) * dm_eps);  // shared by the axis pairs
+        const R P = fmar(R(-2), dm_pi, dm_p), W = fmar(R(-2), dm_wi, dm_w);
+        const R e_x = fmar(R(2), P, C), CmP = C - P;
+        const R e_y = CmP + W, e_z = CmP - W;
+        const R o_z = fmar(R(-4), dm_qz, dm_jz);
+        h[1] = fmar(R(-4), dm_qx, h[1] + e_x);
+        h[2] = fmar(R(4), dm_qx, h[2] + e_x);
+        h[3] = fmar(R(-4), dm_qy, h[3] + e_y);
+        h[4] = fmar(R(4), dm_qy, h[4] + e_y);
+        h[5] = (h[5] + e_z) + o_z;
+        h[6] = (h[6] + e_z) - o_z;
     }
-    static_for<1, QF>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if constexpr (pair_head<L>(i)) {
-            R e = R(0), o = R(0);
-            static_for<1, QF>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                if constexpr (row_parity<L>(k) > 0) cmac<L::M(k, i)>(e, dm[k]);
-                else cmac<L::M(k, i)>(o, dm[k]);
-            });
-            hf[L::opp[i]] += e - o;
-            hf[i] += e + o;
-        }
-    });
-
-    // thermal: n_eq = (T, u T, a_T T, 0...) in deviation form
-    R dn[QG];
-    static_for<0, QG>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        constexpr int kind = H::kind[k];
-        R d;
-        if constexpr (kind == kRho) {
-            d = R(0);
-        } else {
-            const R nk = heat_moment(kc);
-            if constexpr (kind == kJx || kind == kJy || kind == kJz) d = -c.q[kind] * (nk - u[kind - kJx] * T);
-            else if constexpr (kind == kE) d = -c.q[kind] * (nk - c.a_t * dT);
-            else d = -c.q[kind] * nk;
-        }
-        if constexpr (folded_rates<DIM>()) dn[k] = d;  // q carries 1/|N_k|^2 (d = 0 on row 0)
-        else dn[k] = d * R(1.0 / row_norm<H>(k));
-    });
     {
-        R acc = hg[0];
-        static_for<1, QG>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            if constexpr (row_parity<H>(k) > 0) cmac<H::M(k, 0)>(acc, dn[k]);
-        });
-        hg[0] = acc;
+        const R G = fmar(R(8), dm_e, dm_eps);  // shared by the edge pairs
+        const R Pp = dm_p + dm_pi, Wp = dm_w + dm_wi;
+        const R GP = G + Pp;
+        const R e_xy = GP + Wp, e_xz = GP - Wp, e_yz = fmar(R(-2), Pp, G);
+        const R X = dm_qx, Y = dm_qy, Z = dm_jz + dm_qz;
+        const R e7 = e_xy + dm_xy, e9 = e_xy - dm_xy;
+        const R e11 = e_xz + dm_xz, e13 = e_xz - dm_xz;
+        const R e15 = e_yz + dm_yz, e17 = e_yz - dm_yz;
+        const R o7 = (X + Y) + (dm_mx - dm_my), o9 = (X - Y) + (dm_mx + dm_my);
+        const R o11 = (X + Z) + (dm_mz - dm_mx), o13 = (X - Z) - (dm_mx + dm_mz);
+        const R o15 = (Y + Z) + (dm_my - dm_mz), o17 = (Y - Z) + (dm_my + dm_mz);
+        h[7] = (h[7] + e7) + o7;
+        h[8] = (h[8] + e7) - o7;
+        h[9] = (h[9] + e9) + o9;
+        h[10] = (h[10] + e9) - o9;
+        h[11] = (h[11] + e11) + o11;
+        h[12] = (h[12] + e11) - o11;
+        h[13] = (h[13] + e13) + o13;
+        h[14] = (h[14] + e13) - o13;
+        h[15] = (h[15] + e15) + o15;
+        h[16] = (h[16] + e15) - o15;
+        h[17] = (h[17] + e17) + o17;
+        h[18] = (h[18] + e17) - o17;
     }
-    static_for<1, QG>([&](auto ic) {
+    // heat: n_eq = (T, u T, a_T dT, 0, 0) in deviation form
+    const R dn_x = k[k3QJ] * fmar(-ux, T, Dgx);
+    const R dn_y = k[k3QJ] * fmar(-uy, T, Dgy);
+    const R dn_z = k[k3QJ] * fmar(-uz, T, Dgz);
+    const R dn_e = k[k3QE] * fmar(-c.a_t, dT, n_e);
+    const R dn_p = k[k3QP] * n_p, dn_w = k[k3QW] * n_w;
+    g[0] = fmar(R(-6), dn_e, g[0]);
+    {
+        const R e_x = fmar(R(2), dn_p, dn_e), EmP = dn_e - dn_p;
+        const R e_y = EmP + dn_w, e_z = EmP - dn_w;
+        g[1] = (g[1] + e_x) + dn_x;
+        g[2] = (g[2] + e_x) - dn_x;
+        g[3] = (g[3] + e_y) + dn_y;
+        g[4] = (g[4] + e_y) - dn_y;
+        g[5] = (g[5] + e_z) + dn_z;
+        g[6] = (g[6] + e_z) - dn_z;
+    }
+    static_for<0, 19>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if constexpr (pair_head<H>(i)) {
-            R e = R(0), o = R(0);
-            static_for<1, QG>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                if constexpr (row_parity<H>(k) > 0) cmac<H::M(k, i)>(e, dn[k]);
-                else cmac<H::M(k, i)>(o, dn[k]);
-            });
-            hg[H::opp[i]] += e - o;
-            hg[i] += e + o;
-        }
+        dst.sf(i, St::EF::enc(h[i]));
     });
-
-    // store post-collision populations at the node
-    static_for<0, QF>([&](auto ic) {
+    static_for<0, 7>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        dst.sf(i, St::EF::enc(hf[i]));
+        dst.sg(i, St::EG::enc(g[i]));
     });
-    static_for<0, QG>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        dst.sg(i, St::EG::enc(hg[i]));
-    });
-    // unstable: a non-finite density or temperature, or a velocity above
-    // the lattice sound speed c_s = 1/sqrt(3)
-    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    return isfinite(drho + dT) && uu <= R(1.0 / 3.0);
+    // unstable: a non-finite density or temperature, or a speed above the
+    // lattice sound speed c_s = 1/sqrt(3)
+    return isfinite(drho + dT) && ruu * inv_rho <= R(1.0 / 3.0);
 }
+
+// the basis entries written into collide_store_d3
+static_assert(Flow<3>::M(1, 0) == -30 && Flow<3>::M(2, 0) == 12 && Flow<3>::M(1, 1) == -11 &&
+                  Flow<3>::M(2, 1) == -4 && Flow<3>::M(1, 7) == 8 && Flow<3>::M(2, 7) == 1 &&
+                  Flow<3>::M(4, 1) == -4 && Flow<3>::M(4, 7) == 1 && Flow<3>::M(9, 1) == 2 &&
+                  Flow<3>::M(10, 1) == -4 && Flow<3>::M(9, 3) == -1 && Flow<3>::M(10, 3) == 2 &&
+                  Flow<3>::M(9, 7) == 1 && Flow<3>::M(10, 7) == 1 && Flow<3>::M(9, 15) == -2 &&
+                  Flow<3>::M(10, 15) == -2 && Flow<3>::M(11, 3) == 1 && Flow<3>::M(12, 3) == -2 &&
+                  Flow<3>::M(11, 7) == 1 && Flow<3>::M(12, 7) == 1 && Flow<3>::M(11, 11) == -1 &&
+                  Flow<3>::M(13, 9) == -1 && Flow<3>::M(15, 13) == -1 && Flow<3>::M(14, 17) == -1 &&
+                  Flow<3>::M(16, 7) == 1 && Flow<3>::M(17, 7) == -1 && Flow<3>::M(16, 11) == -1 &&
+                  Flow<3>::M(18, 11) == 1 && Flow<3>::M(17, 15) == 1 && Flow<3>::M(18, 15) == -1 &&
+                  Heat<3>::M(4, 0) == -6 && Heat<3>::M(4, 1) == 1 && Heat<3>::M(5, 1) == 2 &&
+                  Heat<3>::M(5, 3) == -1 && Heat<3>::M(6, 3) == 1 && Heat<3>::M(6, 5) == -1,
+              "D3Q19 / D3Q7 basis entries of the written-out collision");
+static_assert(row_norm<Flow<3>>(4) == row_norm<Flow<3>>(6) && row_norm<Flow<3>>(4) == row_norm<Flow<3>>(8) &&
+                  row_norm<Flow<3>>(13) == row_norm<Flow<3>>(14) && row_norm<Flow<3>>(13) == row_norm<Flow<3>>(15) &&
+                  row_norm<Flow<3>>(16) == row_norm<Flow<3>>(17) && row_norm<Flow<3>>(16) == row_norm<Flow<3>>(18) &&
+                  row_norm<Heat<3>>(1) == row_norm<Heat<3>>(2) && row_norm<Heat<3>>(1) == row_norm<Heat<3>>(3),
+              "rows that share a factor of Coef::k3 share their norm");
 
 // Moments, both collisions and the store of one node (hf/hg: the
 // pre-collision deviations).  Returns false if the node's density or
@@ -615,7 +557,7 @@ template <int DIM, class St, class Dst>
 __device__ __forceinline__ bool collide_store(typename St::R* hf, typename St::R* hg,
                                               const Coef<typename St::R>& c, typename St::R tb, const Dst& dst) {
     if constexpr (DIM == 2) return collide_store_d2<St>(hf, hg, c, tb, dst);
-    else return collide_store_nd<DIM, St>(hf, hg, c, tb, dst);
+    else return collide_store_d3<St>(hf, hg, c, tb, dst);
 }
 
 // --------------------------------------------------------- store helpers

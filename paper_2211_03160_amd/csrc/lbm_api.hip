@@ -198,7 +198,8 @@ struct lbm_ctx {
     Geometry geo;
     int cond_axis;
     bool view;    // a cavity owned by a batch: the batch steps and initialises it
-    int32_t steps_per_launch;  // lbm_step: 1, or 2 (two-step tiles, 2D)
+    int32_t steps_per_launch;  // time steps per launch of lbm_step (1-5 in 2D, 1-2 in 3D)
+    int cus;                   // compute units of the device
     char err[512];
 
     void* pop(int k) const { return ws + lay.off_pop[k]; }
@@ -275,7 +276,7 @@ template <class R> Coef<R> make_coef(const lbm_ctx* c) {
         default: return 0.0;
         }
     };
-    // in 2D each kind's rate also carries 1/|M_k|^2 of its rows (folded_rates)
+    // in 2D each kind's rate also carries 1/|M_k|^2 of its rows
     const bool fold = c->p.dim == 2;
     for (int kind = 0; kind < 10; ++kind) {
         const double s = flow_rate(kind);
@@ -284,6 +285,36 @@ template <class R> Coef<R> make_coef(const lbm_ctx* c) {
         k.s[kind] = (R)(s * sf);
         k.b[kind] = (R)((1.0 - 0.5 * s) * sf);
         k.q[kind] = (R)(heat_rate(kind) * sg);
+    }
+    if (c->p.dim == 3) {
+        // the factors of collide_store_d3: d_k / |M_k|^2 with d_k = -s (m_k
+        // - m_k,eq) + (1 - s/2) (M F~)_k, the row's integer factors included
+        auto nf = [](int row) { return (double)row_norm<Flow<3>>(row); };
+        auto ng = [](int row) { return (double)row_norm<Heat<3>>(row); };
+        auto b = [&](int kind) { return 1.0 - 0.5 * flow_rate(kind); };
+        const double sE = flow_rate(kE), sEps = flow_rate(kEps), sQ = flow_rate(kQ), sNu = flow_rate(kNu),
+                     sPi = flow_rate(kPi), sM = flow_rate(kM);
+        k.k3[k3SE] = (R)(-19.0 * sE / nf(1));
+        k.k3[k3BE] = (R)(38.0 * b(kE) / nf(1));
+        k.k3[k3SEps] = (R)(-sEps / nf(2));
+        k.k3[k3BEps] = (R)(-11.0 * b(kEps) / nf(2));
+        k.k3[k3SQ] = (R)(-5.0 / 3.0 * sQ / nf(4));
+        k.k3[k3BQ] = (R)(-(sQ + 2.0 * b(kQ)) / 3.0 / nf(4));
+        k.k3[k3SP] = (R)(-sNu / nf(9));
+        k.k3[k3BP] = (R)(-2.0 * b(kNu) / nf(9));
+        k.k3[k3SPi] = (R)(-sPi / nf(10));
+        k.k3[k3BPi] = (R)(b(kPi) / nf(10));
+        k.k3[k3SW] = (R)(-sNu / nf(11));
+        k.k3[k3BW] = (R)(-2.0 * b(kNu) / nf(11));
+        k.k3[k3SWi] = (R)(-sPi / nf(12));
+        k.k3[k3BWi] = (R)(b(kPi) / nf(12));
+        k.k3[k3SO] = (R)(-sNu / nf(13));
+        k.k3[k3BO] = (R)(b(kNu) / nf(13));
+        k.k3[k3SM] = (R)(-sM / nf(16));
+        k.k3[k3QJ] = (R)(-heat_rate(kJx) / ng(1));
+        k.k3[k3QE] = (R)(-heat_rate(kE) / ng(4));
+        k.k3[k3QP] = (R)(-heat_rate(kNu) / ng(5));
+        k.k3[k3QW] = (R)(-heat_rate(kNu) / ng(6));
     }
     k.a_t = (R)v[LBM_D_A_T];
     k.gbeta = (R)v[LBM_D_GBETA];
@@ -575,12 +606,28 @@ template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
     }
 }
 
-// Planes per z segment of the 3D two-step kernel: each segment repeats the
-// first step on one plane below and one above it, and segments give the
-// launch enough blocks to fill every compute unit several times over.
-#ifndef LBM_STREAM3_PLANES
-#define LBM_STREAM3_PLANES 48
-#endif
+// z segments of the 3D two-step kernel.  Each segment repeats the first
+// step on one plane below and one above it, and its block holds a compute
+// unit's LDS for the whole segment, so a launch runs in rounds: each XCD
+// takes its share of blocks `resident` per compute unit at a time.  The
+// count chosen minimises rounds x (planes per segment + 2), the plane
+// steps of the slowest compute unit (fewer segments on a tie).
+uint32_t stream3_segments(uint32_t nz, uint32_t tiles, int cus, int resident) {
+    const uint64_t slots = (uint64_t)std::max(cus / kXcd, 1) * (uint64_t)std::max(resident, 1);
+    uint32_t best = 1;
+    uint64_t best_cost = UINT64_MAX;
+    for (uint32_t segs = 1; segs <= nz; ++segs) {
+        const uint64_t planes = (nz + segs - 1) / segs;
+        if (segs > 1 && (nz + planes - 1) / planes < segs) continue;  // same split as fewer segments
+        const uint64_t per_xcd = ((uint64_t)tiles * segs + kXcd - 1) / kXcd;
+        const uint64_t cost = (per_xcd + slots - 1) / slots * (planes + 2);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = segs;
+        }
+    }
+    return best;
+}
 
 // k launches of the 3D two-step kernel, A -> B, advancing t by 2 k
 template <class St> void stream3_launches(lbm_ctx* c, int64_t k) {
@@ -589,7 +636,13 @@ template <class St> void stream3_launches(lbm_ctx* c, int64_t k) {
     a.c = make_coef<typename St::R>(c);
     a.tiles_x = (c->geo.nx + kT3OutX - 1) / kT3OutX;
     a.tiles_y = (c->geo.ny + kT3OutY - 1) / kT3OutY;
-    a.seg_planes = LBM_STREAM3_PLANES;
+    static const int resident = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream3_kernel<St>, kT3Threads, 0) != hipSuccess) n = 1;
+        return std::max(n, 1);
+    }();
+    const uint32_t segs = stream3_segments(c->geo.nz, a.tiles_x * a.tiles_y, c->cus, resident);
+    a.seg_planes = (c->geo.nz + segs - 1) / segs;
     a.segs = (c->geo.nz + a.seg_planes - 1) / a.seg_planes;
     const uint32_t blocks = a.tiles_x * a.tiles_y * a.segs;
     a.blocks_per_xcd = (blocks + kXcd - 1) / kXcd;
@@ -655,9 +708,10 @@ lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void
     if ((uintptr_t)d_workspace % kAlign) return set_err(g_err, LBM_E_INVALID, "workspace not 256-byte aligned");
     if (bytes < lay.total)
         return set_err(g_err, LBM_E_INVALID, "workspace of %zu bytes is smaller than the %zu needed", bytes, lay.total);
-    int dev = 0;
+    int dev = 0, cus = 0;
     HIP_TRY(g_err, hipGetDevice(&dev));
     if (!is_device_ptr(d_workspace)) return set_err(g_err, LBM_E_INVALID, "workspace is not device memory");
+    HIP_TRY(g_err, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return set_err(g_err, LBM_E_INVALID, "out of host memory");
@@ -665,6 +719,7 @@ lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void
     c->d = d;
     c->lay = lay;
     c->device = dev;
+    c->cus = cus;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char*)d_workspace;
     c->cur = 0;

@@ -181,8 +181,10 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
     constexpr int kSlot = kT3Cross * kT3Threads;  // elements of one LDS ring slot
 
     R rm[kT3Own] = {}, rz[kT3Own] = {}, rp[kT3Own] = {}, rn[kT3Own];  // register ring: planes p-1, p, p+1, new
-    R pf[QF], pg[QG];    // step-1 sources of the next plane
-    R pf2[QF], pg2[QG];  // and of the plane after it, in flight
+    // step-1 sources: two register sets, used alternately by the plane loop
+    // (unrolled twice), so the set gathered for the next iteration is never
+    // copied and stays in flight until that iteration reads it
+    R pfA[QF], pgA[QG], pfB[QF], pgB[QG];
 
     // the plane of step 1 for ring position q (relative to z0 - 1), wrapped
     // on a periodic z axis, -1 if it lies beyond a wall or is not needed.
@@ -218,8 +220,8 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
             dg[i] = src.template pull_g<i, ex, ey, ez, H::opp[i]>(out);
         });
     };
-    // step 1 of plane zq from the gathered sources into LDS slot s and rn
-    auto step1 = [&](int32_t zq, int s) __attribute__((always_inline)) {
+    // step 1 of plane zq from the gathered sources pf, pg into LDS slot s and rn
+    auto step1 = [&](int32_t zq, int s, const R (&pf)[QF], const R (&pg)[QG]) __attribute__((always_inline)) {
         const Neighbours nb = neighbours(g, x, y, (uint32_t)zq);
         const bool own = own_xy && zq >= z0 && zq < z1;
         step_node<3, St, Walls>(g, a.c, nb, x, y, (uint32_t)zq, PreSrc<St, QF, QG>{pf, pg},
@@ -234,14 +236,23 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
             rp[i] = rn[i];
         });
     };
-    // step 2 of plane p from LDS slots sm, sz, sp (planes p - 1, p, p + 1),
-    // stored to global memory for the nodes the tile owns
-    auto step2 = [&](int32_t p, int sm, int sz, int sp) __attribute__((always_inline)) {
+    // step 2 of plane p from LDS slots sm, sz, sp (planes p - 1, p, p + 1)
+    // into registers (ef, eg, encoded); store2 writes them to global memory
+    // for the nodes the tile owns.
+    typename St::TF ef[QF];
+    typename St::TG eg[QG];
+    auto step2 = [&](int32_t p, int sm, int sz, int sp, typename St::TF (&ef)[QF],
+                     typename St::TG (&eg)[QG]) __attribute__((always_inline)) {
         const Neighbours nb = neighbours(g, x, y, (uint32_t)p);
         const RingSrc<St> src{lds, rm, rz, rp, nbr, sm * kSlot, sz * kSlot, sp * kSlot};
-        // stores through a buffer resource based at the first storage tile
-        // of the wavefront's rows (a wavefront-uniform base; its two rows
-        // and their halo span at most 2 nx + 64 nodes)
+        step_node<3, St, Walls>(g, a.c, nb, x, y, (uint32_t)p, src, EncDst<St, QF, QG>{ef, eg},
+                                BufFlux3{rflux, a.slot2, a.flux_bytes, own_xy});
+    };
+    auto store2 = [&](int32_t p, const typename St::TF (&ef)[QF], const typename St::TG (&eg)[QG])
+                      __attribute__((always_inline)) {
+        // through a buffer resource based at the first storage tile of the
+        // wavefront's rows (a wavefront-uniform base; its two rows and
+        // their halo span at most 2 nx + 64 nodes)
         const uint32_t row0 = g.nx * (wrow + g.ny * (uint32_t)p);
         const uint32_t t0 = row0 / kTile, tiles = (2 * g.nx + kTile - 1) / kTile + 2;
         const uint32_t fb = tiles * (uint32_t)(QF * kTile * sizeof(typename St::TF));
@@ -250,7 +261,8 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
         const OwnedBufDst<St, QF, QG> dst(buffer_rsrc(a.fdst + (size_t)t0 * (QF * kTile), fb),
                                           buffer_rsrc(a.gdst + (size_t)t0 * (QG * kTile), gb), fb, gb,
                                           idx - t0 * kTile, own_xy);
-        step_node<3, St, Walls>(g, a.c, nb, x, y, (uint32_t)p, src, dst, BufFlux3{rflux, a.slot2, a.flux_bytes, own_xy});
+        static_for<0, QF>([&](auto ic) { dst.sf(decltype(ic)::value, ef[decltype(ic)::value]); });
+        static_for<0, QG>([&](auto ic) { dst.sg(decltype(ic)::value, eg[decltype(ic)::value]); });
     };
 
     // prologue: step 1 of ring positions 0, 1, 2 (planes z0 - 1, z0, z0 + 1)
@@ -259,34 +271,52 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
     for (int q = 0; q < 3; ++q) {
         const int32_t zq = step1_plane(q);
         if (!Walls || zq >= 0) {
-            gather(zq, pf, pg);
-            step1(zq, q);
+            gather(zq, pfA, pgA);
+            step1(zq, q, pfA, pgA);
         }
         rotate();
     }
     int32_t zn = step1_plane(3);
-    if (!Walls || zn >= 0) gather(zn, pf, pg);
+    if (!Walls || zn >= 0) gather(zn, pfA, pgA);
     __syncthreads();
-    // plane p = z0 + r needs ring positions r, r + 1, r + 2 (LDS slots s0,
+    // Plane p = z0 + r needs ring positions r, r + 1, r + 2 (LDS slots s0,
     // s0 + 1, s0 + 2 mod 3 with s0 = r mod 3); then step 1 of position
     // r + 3 (plane p + 2, its sources gathered one iteration earlier) goes
     // into slot s0, which step 2 has just read, while the sources of
-    // position r + 4 are loaded
+    // position r + 4 are loaded.  Loads and stores retire through one in-order counter (at most 63 in
+    // flight), and a store's data registers are read after it issues (so
+    // overwriting them waits for the store).  The order below keeps both
+    // waits short: the sources that step 1 of iteration r reads were
+    // gathered in iteration r - 1 into the other register set of two (no
+    // copy, so they stay in flight), and only this iteration's stores and
+    // gather are younger (52 operations); step 2 of iteration r + 1
+    // overwrites the store data of iteration r after step 1 has run.
     int s0 = 0;
-    for (int32_t r = 0; r < z1 - z0; ++r) {
+    auto iteration = [&](int32_t r, const R (&cf)[QF], const R (&cg)[QG], R (&nf)[QF], R (&ng)[QG])
+                         __attribute__((always_inline)) {
         const int s1 = s0 == 2 ? 0 : s0 + 1, s2 = s1 == 2 ? 0 : s1 + 1;
-        const int32_t zn2 = step1_plane(r + 4);
-        if (!Walls || zn2 >= 0) gather(zn2, pf2, pg2);  // loads in flight for a whole iteration
-        step2(z0 + r, s0, s1, s2);
+        step2(z0 + r, s0, s1, s2, ef, eg);
+        store2(z0 + r, ef, eg);
         __syncthreads();
-        if (!Walls || zn >= 0) step1(zn, s0);
+        const int32_t zn2 = step1_plane(r + 4);
+        if (!Walls || zn2 >= 0) gather(zn2, nf, ng);  // read by step 1 of the next iteration
+        // keep the compiler from sinking those loads below step 1's
+        // arithmetic (which would leave them half an iteration instead of a
+        // whole one): nothing is scheduled across this point
+        __builtin_amdgcn_sched_barrier(0);
+        if (!Walls || zn >= 0) step1(zn, s0, cf, cg);
         rotate();
-        static_for<0, QF>([&](auto ic) { pf[decltype(ic)::value] = pf2[decltype(ic)::value]; });
-        static_for<0, QG>([&](auto ic) { pg[decltype(ic)::value] = pg2[decltype(ic)::value]; });
         zn = zn2;
         __syncthreads();
         s0 = s1;
+    };
+    const int32_t planes = z1 - z0;
+    int32_t r = 0;
+    for (; r + 1 < planes; r += 2) {
+        iteration(r, pfA, pgA, pfB, pgB);
+        iteration(r + 1, pfB, pgB, pfA, pgA);
     }
+    if (r < planes) iteration(r, pfA, pgA, pfB, pgB);
 }
 
 template <class St>
