@@ -386,8 +386,9 @@ def main():
         "rb2d_8193_fp16": (W.with_storage(cfg32, "fp16"), Wm, K),
         "rb2d_8193_bf16": (W.with_storage(cfg32, "bf16"), Wm, K),
         "rb2d_8193_mixed": (W.with_storage(cfg32, "mixed"), Wm, K),
-        "rb3d_385_fp32": (W.C2["cfg"], 5, W.C2["steps"]),
-        "rb3d_385_fp64": (W.with_storage(W.C2["cfg"], "fp64"), 5, W.C2["steps"]),
+        "rb3d_385_fp32": (W.C2["cfg"], 6, W.C2["steps"]),
+        "rb3d_385_fp32_1": (W.C2["cfg"], 6, W.C2["steps"]),
+        "rb3d_385_fp64": (W.with_storage(W.C2["cfg"], "fp64"), 6, W.C2["steps"]),
         "rb3d_385_fp16": (W.with_storage(W.C2["cfg"], "fp16"), 5, W.C2["steps"]),
         "rb3d_385_bf16": (W.with_storage(W.C2["cfg"], "bf16"), 5, W.C2["steps"]),
         "rb3d_385_mixed": (W.with_storage(W.C2["cfg"], "mixed"), 5, W.C2["steps"]),
@@ -461,7 +462,7 @@ def main():
             variants[name] = r
             log(name, json.dumps(r))
         N3 = 385 ** 3
-        ref3 = run_case(cases["rb3d_385_fp64"][0], 5, W.C2["steps"], W.C2["seed"], W.C2["noise"])
+        ref3 = run_case(cases["rb3d_385_fp64"][0], 6, W.C2["steps"], W.C2["seed"], W.C2["noise"])
         ref3["roofline"] = hbm_roofline(ref3, N3, "lbm::step_kernel<3, StF64>", ceil["copy"]["gbs"])
         variants["rb3d_385_fp64"] = ref3
         log("rb3d_385_fp64", json.dumps(ref3))
@@ -471,7 +472,10 @@ def main():
             r["nu_rel_err_vs_fp64"] = nu_err(r["nu"], ref3["nu"])
             r["re_rel_err_vs_fp64"] = rel(r["re"], ref3["re"])
             r["hbm_frac"] = r["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
-            r["roofline"] = hbm_roofline(r, N3, "lbm::step_kernel<3, ...>", ceil["copy"]["gbs"])
+            st = {"rb3d_385_fp32": "StF32", "rb3d_385_fp16": "StF16", "rb3d_385_bf16": "StBF16",
+                  "rb3d_385_mixed": "StMix"}[name]
+            k3 = f"lbm::stream3_kernel<{st}>" if r["steps_per_launch"] == 2 else f"lbm::step_kernel<3, {st}>"
+            r["roofline"] = hbm_roofline(r, N3, k3, ceil["copy"]["gbs"])
             variants[name] = r
             log(name, json.dumps(r))
 

@@ -179,9 +179,9 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
 /* Steps per kernel launch of lbm_step: 1 .. 5 in 2D (5 with FP32 storage
- * only), 1 or 2 in 3D.  A 2D context starts with the count measured
- * fastest for its storage: 5 (FP32), 4 (FP16-f+FP32-g, BF16), 3 (FP16),
- * 2 (FP64); 3D contexts with 1.
+ * only), 1 or 2 in 3D.  A context starts with the count measured
+ * fastest for its storage: in 2D 5 (FP32), 4 (FP16-f+FP32-g, BF16), 3
+ * (FP16), 2 (FP64); in 3D 2 (FP32) and 1 (the others).
  * With k > 1 in 2D, each wavefront walks down a strip of columns row by
  * row, keeping the last rows of step t and of the intermediate steps in
  * registers, and writes step t+k; in 3D (k = 2) a block walks a 32 x 16

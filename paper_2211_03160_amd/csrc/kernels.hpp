@@ -59,6 +59,11 @@ constexpr int kTile = 64;    // nodes per storage tile (one wavefront)
 template <int Q> __host__ __device__ __forceinline__ uint32_t pop_at(uint32_t node, int i) {
     return (node / kTile) * (uint32_t)(Q * kTile) + (uint32_t)(i * kTile) + node % kTile;
 }
+// the same for node < 2^30, where the tile number fits the 24-bit multiply
+// (a full-rate instruction; the 32-bit one issues at a quarter of the rate)
+template <int Q> __device__ __forceinline__ uint32_t pop_at24(uint32_t node, int i) {
+    return __umul24(node / kTile, (uint32_t)(Q * kTile)) + (uint32_t)(i * kTile) + node % kTile;
+}
 
 // ------------------------------------------------------------------ storage
 // Element codecs: stored type T, dec() to the compute type, enc() from it.
@@ -620,7 +625,8 @@ struct PtrFlux {  // per-face arrays
 // population plane there.  In global memory a displacement across a
 // periodic face wraps (the offsets are prepared per node); in an LDS tile
 // the halo already holds the wrapped neighbours.
-template <class St, int QF, int QG, bool O32 = false> struct GlobalSrc {
+// Pull sources in global memory; U24: every node index is below 2^30.
+template <class St, int QF, int QG, bool O32 = false, bool U24 = false> struct GlobalSrc {
     const typename St::TF* f;
     const typename St::TG* g;
     uint32_t idx;
@@ -629,8 +635,12 @@ template <class St, int QF, int QG, bool O32 = false> struct GlobalSrc {
         return (uint32_t)((int32_t)idx + (sx < 0 ? oxm : sx > 0 ? oxp : 0) + (sy < 0 ? oym : sy > 0 ? oyp : 0) +
                           (sz < 0 ? ozm : sz > 0 ? ozp : 0));
     }
-    __device__ typename St::TF lf(int i, uint32_t node) const { return *elem<O32>(f, pop_at<QF>(node, i)); }
-    __device__ typename St::TG lg(int i, uint32_t node) const { return *elem<O32>(g, pop_at<QG>(node, i)); }
+    __device__ typename St::TF lf(int i, uint32_t node) const {
+        return *elem<O32>(f, U24 ? pop_at24<QF>(node, i) : pop_at<QF>(node, i));
+    }
+    __device__ typename St::TG lg(int i, uint32_t node) const {
+        return *elem<O32>(g, U24 ? pop_at24<QG>(node, i) : pop_at<QG>(node, i));
+    }
     // both cases from one node index and one plane: a single load serves either
     template <int i, int ex, int ey, int ez, int o> __device__ typename St::R pull_f(bool out) const {
         return St::EF::dec(lf(out ? o : i, out ? at(0, 0, 0) : at(-ex, -ey, -ez)));
@@ -659,12 +669,12 @@ __device__ __forceinline__ Neighbours neighbours(const Geometry& g, uint32_t x, 
     return n;
 }
 
-template <class St, int QF, int QG, bool O32 = false>
-__device__ __forceinline__ GlobalSrc<St, QF, QG, O32> global_src(const Geometry& g, const Neighbours& n,
-                                                                 const typename St::TF* f,
-                                                                 const typename St::TG* gp, uint32_t idx) {
+template <class St, int QF, int QG, bool O32 = false, bool U24 = false>
+__device__ __forceinline__ GlobalSrc<St, QF, QG, O32, U24> global_src(const Geometry& g, const Neighbours& n,
+                                                                      const typename St::TF* f,
+                                                                      const typename St::TG* gp, uint32_t idx) {
     const int32_t nx = (int32_t)g.nx, sy = nx, sz = nx * (int32_t)g.ny;
-    GlobalSrc<St, QF, QG, O32> s;
+    GlobalSrc<St, QF, QG, O32, U24> s;
     s.f = f;
     s.g = gp;
     s.idx = idx;
@@ -842,14 +852,16 @@ template <class St, int QF, int QG> struct EncDst {
 // the compiler unsure it was issued, so it then waits for more of the
 // memory operations after a load than the load needs; the buffer form
 // drops the other lanes' stores instead and keeps the code straight-line.
-template <class St, int QF, int QG> struct OwnedBufDst {
+template <class St, int QF, int QG, bool U24 = false> struct OwnedBufDst {
     __amdgpu_buffer_rsrc_t rf, rg;
     uint32_t of, og;  // byte offset of the node's first plane, or beyond the buffer
+    // idx: the node's index from the first node of the buffers (below 2^30
+    // with U24)
     __device__ OwnedBufDst(__amdgpu_buffer_rsrc_t rf_, __amdgpu_buffer_rsrc_t rg_, uint32_t f_bytes,
                            uint32_t g_bytes, uint32_t idx, bool own)
         : rf(rf_), rg(rg_),
-          of(own ? pop_at<QF>(idx, 0) * (uint32_t)sizeof(typename St::TF) : f_bytes),
-          og(own ? pop_at<QG>(idx, 0) * (uint32_t)sizeof(typename St::TG) : g_bytes) {}
+          of(own ? (U24 ? pop_at24<QF>(idx, 0) : pop_at<QF>(idx, 0)) * (uint32_t)sizeof(typename St::TF) : f_bytes),
+          og(own ? (U24 ? pop_at24<QG>(idx, 0) : pop_at<QG>(idx, 0)) * (uint32_t)sizeof(typename St::TG) : g_bytes) {}
     __device__ void sf(int i, typename St::TF v) const {
         buffer_store(v, rf, of + (uint32_t)(i * kTile * sizeof(typename St::TF)));
     }

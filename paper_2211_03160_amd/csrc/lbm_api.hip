@@ -506,7 +506,11 @@ template <class St> constexpr bool five_steps() {
 // its shared terms (GLUPS, best segment length each): FP32 at three / four /
 // five steps 103 / 149 / 171; FP16 169 / 161 / 151; BF16 169 / 185 / 177;
 // FP16-f+FP32-g 172 (four) / 165 (five).
-int32_t default_steps_per_launch(int32_t storage) {
+int32_t default_steps_per_launch(int32_t dim, int32_t storage) {
+    // 3D: the two-step plane ring beats one step per launch with FP32
+    // storage only (with 16-bit storage a one-step launch moves half the
+    // bytes and is faster)
+    if (dim == 3) return storage == LBM_FP32 ? 2 : 1;
     switch (storage) {
     case LBM_FP32: return 5;
     case LBM_MIXED_F16_G32: return 4;
@@ -535,7 +539,10 @@ bool streamable(const lbm_ctx* c) {
 // plane with 32-bit byte offsets
 bool streamable3(const lbm_ctx* c) {
     const size_t lim = ((size_t)1 << 32) - 65536;
-    return ((size_t)c->geo.nx * 2 / kTile + 3) * kTile * qf_of(3) * 8 < lim &&
+    // node indices below 2^30 (24-bit tile numbers in the gather), the store
+    // window of a wavefront's rows and the flux area under 4 GiB
+    return (size_t)c->geo.N <= ((size_t)1 << 30) &&
+           ((size_t)c->geo.nx * 2 / kTile + 3) * kTile * qf_of(3) * 8 < lim &&
            2 * c->lay.flux_doubles * sizeof(double) < lim;
 }
 
@@ -724,7 +731,7 @@ lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void
     c->ws = (char*)d_workspace;
     c->cur = 0;
     c->t = -1;
-    c->steps_per_launch = p->dim == 2 && !view ? default_steps_per_launch(p->storage) : 1;
+    c->steps_per_launch = view ? 1 : default_steps_per_launch(p->dim, p->storage);
     Geometry& g = c->geo;
     g.nx = p->n[0];
     g.ny = p->n[1];

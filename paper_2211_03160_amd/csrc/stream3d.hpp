@@ -204,7 +204,7 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
     auto gather = [&](int32_t zq, R(&df)[QF], R(&dg)[QG]) __attribute__((always_inline)) {
         const Neighbours nb = neighbours(g, x, y, (uint32_t)zq);
         const uint32_t idx = x + g.nx * (y + g.ny * (uint32_t)zq);
-        const auto src = global_src<St, QF, QG>(g, nb, a.fsrc, a.gsrc, idx);
+        const auto src = global_src<St, QF, QG, false, true>(g, nb, a.fsrc, a.gsrc, idx);
         static_for<0, QF>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
@@ -258,9 +258,9 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
         const uint32_t fb = tiles * (uint32_t)(QF * kTile * sizeof(typename St::TF));
         const uint32_t gb = tiles * (uint32_t)(QG * kTile * sizeof(typename St::TG));
         const uint32_t idx = x + g.nx * (y + g.ny * (uint32_t)p);
-        const OwnedBufDst<St, QF, QG> dst(buffer_rsrc(a.fdst + (size_t)t0 * (QF * kTile), fb),
-                                          buffer_rsrc(a.gdst + (size_t)t0 * (QG * kTile), gb), fb, gb,
-                                          idx - t0 * kTile, own_xy);
+        const OwnedBufDst<St, QF, QG, true> dst(buffer_rsrc(a.fdst + (size_t)t0 * (QF * kTile), fb),
+                                                buffer_rsrc(a.gdst + (size_t)t0 * (QG * kTile), gb), fb, gb,
+                                                idx - t0 * kTile, own_xy);
         static_for<0, QF>([&](auto ic) { dst.sf(decltype(ic)::value, ef[decltype(ic)::value]); });
         static_for<0, QG>([&](auto ic) { dst.sg(decltype(ic)::value, eg[decltype(ic)::value]); });
     };

@@ -131,6 +131,9 @@ def test_steps_per_launch_arguments():
         with pytest.raises(lbm.LBMError) as e:
             c64.steps_per_launch = k
         assert e.value.status == -5
+    defaults3 = {"fp32": 2, "mixed": 1, "fp16": 1, "bf16": 1, "fp64": 1}
+    for st, k in defaults3.items():
+        assert lbm.Cavity(W.rayleigh_benard(3, (9, 9, 9), ra=1e4, pr=0.71, storage=st)).steps_per_launch == k
     c3 = lbm.Cavity(W.rayleigh_benard(3, (9, 9, 9), ra=1e4, pr=0.71, storage="fp32"))
     for k in (3, 4, 5):
         with pytest.raises(lbm.LBMError) as e:
