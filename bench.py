@@ -34,9 +34,11 @@ METRIC = "GLUPS & %HBM peak, FP32 vs FP16-store, 8193² D2Q9+D2Q5 / 385³ D3Q19+
 # the kernels and their launch configuration (strip segments, steps per
 # launch): HBM traffic counters are valid for this hash only
 KERNEL_SOURCES = ["paper_2211_03160_amd/csrc/kernels.hpp", "paper_2211_03160_amd/csrc/lattice.hpp",
-                  "paper_2211_03160_amd/csrc/lbm_api.hip"]
+                  "paper_2211_03160_amd/csrc/stream3d.hpp", "paper_2211_03160_amd/csrc/lbm_api.hip"]
 TRAFFIC_FILES = {5: os.path.join(ROOT, "profiles", "stream5_d2q9_fp32_8193_counters.txt"),
                  1: os.path.join(ROOT, "profiles", "step_d2q9_fp32_8193_counters.txt")}
+TRAFFIC_FILES_3D = {2: os.path.join(ROOT, "profiles", "stream3d_d3q19_fp32_385_counters.txt"),
+                    1: os.path.join(ROOT, "profiles", "step_d3q19_fp32_385_counters.txt")}
 # FP32 operations per 2D lattice update in the kernels' formulation (adds,
 # subtracts, multiplies and the reciprocal 1 each, fused multiply-adds 2):
 # the written-out D2Q9 + D2Q5 collision with its shared terms, its moments
@@ -62,11 +64,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(steps_per_launch):
-    """HBM bytes per launch of the step kernel (two steps or one) from the
-    committed rocprofv3 counter runs, if they were taken on the current
-    kernel source."""
-    path = TRAFFIC_FILES.get(steps_per_launch)
+def read_traffic(steps_per_launch, files=TRAFFIC_FILES):
+    """HBM bytes per launch of an FP32 step kernel (several steps per launch
+    or one) from the committed rocprofv3 counter runs, if they were taken on
+    the current kernel source."""
+    path = files.get(steps_per_launch)
     if path is None or not os.path.exists(path):
         return None
     kv = {}
@@ -476,6 +478,8 @@ def main():
                   "rb3d_385_mixed": "StMix"}[name]
             k3 = f"lbm::stream3_kernel<{st}>" if r["steps_per_launch"] == 2 else f"lbm::step_kernel<3, {st}>"
             r["roofline"] = hbm_roofline(r, N3, k3, ceil["copy"]["gbs"])
+            if name == "rb3d_385_fp32":
+                r["roofline"]["traffic"] = read_traffic(r["steps_per_launch"], TRAFFIC_FILES_3D)
             variants[name] = r
             log(name, json.dumps(r))
 
