@@ -64,7 +64,12 @@ def test_config1_8193_fp32_every_node_vs_oracle():
 
 @pytest.mark.timeout(900)
 def test_config2_385_fp32_every_node_vs_oracle():
+    """Two steps: one launch of the 3D two-step FP32 kernel, the one the
+    385^3 leg times."""
     c2 = W.C2
+    g = lbm.Cavity(c2["cfg"])
+    assert g.steps_per_launch == 2
+    del g
     _compare_full(c2["cfg"], 2, c2["seed"], c2["noise"])
 
 
