@@ -198,6 +198,18 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n);
 lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps);
 int32_t lbm_get_steps_per_launch(const lbm_ctx* c); /* 0 for NULL */
 
+/* Debug mode (on = 1; off = 0, the default): before every kernel launch of
+ * lbm_step, the population buffer the launch writes is filled with all-one
+ * bits (NaN in every storage type; the padding beyond the last node stays
+ * zero).  The pull scheme reads only the state and writes only the other
+ * buffer, so a launch that leaves any population of any node unwritten
+ * makes that value NaN in the new state, where lbm_diagnostics counts it
+ * (nonfinite); with every node written the results are bitwise those of
+ * the normal mode.  Costs one extra pass over the buffer per launch.
+ * LBM_E_INVALID for other values of on, LBM_E_STATE for a batch member.  */
+lbm_status lbm_set_debug_poison(lbm_ctx* c, int32_t on);
+int32_t lbm_get_debug_poison(const lbm_ctx* c); /* 0 for NULL */
+
 /* Moments of the current state at time t (the pre-collision moments
  * rho = sum f, u = (sum e f + F/2)/rho, T = sum g of Section 2.2),
  * computed in FP64 from the stored populations.  Each pointer may be

@@ -1453,6 +1453,11 @@ __global__ __launch_bounds__(kBlock) void zero_bytes_kernel(unsigned char* p, ui
     for (uint32_t k = threadIdx.x; k < n; k += kBlock) p[k] = 0;
 }
 
+__global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void fill_kernel(double* p, size_t n, double v) {
     for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
         p[i] = v;

@@ -200,6 +200,7 @@ struct lbm_ctx {
     bool view;    // a cavity owned by a batch: the batch steps and initialises it
     int32_t steps_per_launch;  // time steps per launch of lbm_step (1-5 in 2D, 1-2 in 3D)
     int cus;                   // compute units of the device
+    bool poison;               // debug: fill the destination state with NaN before every launch
     char err[512];
 
     void* pop(int k) const { return ws + lay.off_pop[k]; }
@@ -430,24 +431,39 @@ lbm_status launch_init(lbm_ctx* c, int mode, uint32_t n0, uint32_t cnt, uint64_t
 
 // both population buffers: zero the bytes that hold no node (the lanes of
 // the last storage tile beyond N, the alignment gap after the f arrays)
-lbm_status clear_tails(lbm_ctx* c) {
+void clear_tails_of(lbm_ctx* c, int k) {
     const uint32_t N = c->geo.N;
     const uint32_t qf = qf_of(c->p.dim), qg = qg_of(c->p.dim);
     const uint32_t ef = (uint32_t)elem_f(c->p.storage), eg = (uint32_t)elem_g(c->p.storage);
     const size_t f_used = (size_t)(N + kTile - 1) / kTile * kTile * qf * ef;
-    for (int k = 0; k < 2; ++k) {
-        unsigned char* base = (unsigned char*)c->pop(k);
-        if (N % kTile) {
-            hipLaunchKernelGGL(clear_tail_kernel, dim3(1), dim3(kBlock), 0, c->stream, base, N, qf, ef);
-            hipLaunchKernelGGL(clear_tail_kernel, dim3(1), dim3(kBlock), 0, c->stream, base + c->lay.f_bytes, N,
-                               qg, eg);
-        }
-        if (c->lay.f_bytes > f_used)
-            hipLaunchKernelGGL(zero_bytes_kernel, dim3(1), dim3(kBlock), 0, c->stream, base + f_used,
-                               (uint32_t)(c->lay.f_bytes - f_used));
+    unsigned char* base = (unsigned char*)c->pop(k);
+    if (N % kTile) {
+        hipLaunchKernelGGL(clear_tail_kernel, dim3(1), dim3(kBlock), 0, c->stream, base, N, qf, ef);
+        hipLaunchKernelGGL(clear_tail_kernel, dim3(1), dim3(kBlock), 0, c->stream, base + c->lay.f_bytes, N, qg,
+                           eg);
     }
+    if (c->lay.f_bytes > f_used)
+        hipLaunchKernelGGL(zero_bytes_kernel, dim3(1), dim3(kBlock), 0, c->stream, base + f_used,
+                           (uint32_t)(c->lay.f_bytes - f_used));
+}
+
+lbm_status clear_tails(lbm_ctx* c) {
+    for (int k = 0; k < 2; ++k) clear_tails_of(c, k);
     HIP_TRY(c->err, hipGetLastError());
     return LBM_OK;
+}
+
+// Debug mode: before a launch writes the population buffer that is not the
+// state, fill every node's populations there with all-one bits (NaN in
+// every storage type) and restore the zero tails, so that a node the
+// launch fails to write reads as NaN in the next state.  A fill kernel,
+// not a memset, so that a captured graph replays it correctly.
+void poison_dst(lbm_ctx* c) {
+    if (!c->poison) return;
+    const size_t words = c->lay.pop_bytes / 4;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<size_t>(grid_for(words), 4096)), dim3(kBlock), 0,
+                       c->stream, (uint32_t*)c->pop(1 - c->cur), words, 0xFFFFFFFFu);
+    clear_tails_of(c, 1 - c->cur);
 }
 
 lbm_status zero_flux(lbm_ctx* c) {
@@ -606,6 +622,7 @@ template <class St, int NS, int D> void stream_launches(lbm_ctx* c, int64_t k) {
         a.fdst = B.f;
         a.gdst = B.g;
         a.t_parity = (int32_t)(c->t & 1);
+        poison_dst(c);
         if (o32) hipLaunchKernelGGL((stream_kernel<St, NWB, true, NS, D>), grid, block, 0, c->stream, a);
         else hipLaunchKernelGGL((stream_kernel<St, NWB, false, NS, D>), grid, block, 0, c->stream, a);
         c->cur = 1 - c->cur;
@@ -665,6 +682,7 @@ template <class St> void stream3_launches(lbm_ctx* c, int64_t k) {
         // step j of the launch writes flux slot (t + j) mod 2
         a.slot1 = (uint32_t)(((c->t + 1) & 1) * c->lay.flux_doubles);
         a.slot2 = (uint32_t)((c->t & 1) * c->lay.flux_doubles);
+        poison_dst(c);
         hipLaunchKernelGGL((stream3_kernel<St>), grid, block, 0, c->stream, a);
         c->cur = 1 - c->cur;
         c->t += 2;
@@ -727,6 +745,7 @@ lbm_status create_ctx(const lbm_params* p, void* d_workspace, size_t bytes, void
     c->lay = lay;
     c->device = dev;
     c->cus = cus;
+    c->poison = false;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char*)d_workspace;
     c->cur = 0;
@@ -887,6 +906,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
             a.gdst = B.g;
             const int slot = (int)((c->t + 1) & 1);
             for (int f = 0; f < 6; ++f) a.flux[f] = c->flux(slot, f);
+            poison_dst(c);
             hipLaunchKernelGGL((step_kernel<DIM, St>), grid, block, 0, c->stream, a);
             c->cur = 1 - c->cur;
             c->t += 1;
@@ -915,6 +935,17 @@ lbm_status lbm_set_steps_per_launch(lbm_ctx* c, int32_t steps) {
 }
 
 int32_t lbm_get_steps_per_launch(const lbm_ctx* c) { return c ? c->steps_per_launch : 0; }
+
+lbm_status lbm_set_debug_poison(lbm_ctx* c, int32_t on) {
+    lbm_status st = enter(c);
+    if (st) return st;
+    if (c->view) return reject_view(c, "lbm_set_debug_poison");
+    if (on != 0 && on != 1) return set_err(c->err, LBM_E_INVALID, "on must be 0 or 1");
+    c->poison = on == 1;
+    return LBM_OK;
+}
+
+int32_t lbm_get_debug_poison(const lbm_ctx* c) { return c && c->poison ? 1 : 0; }
 
 lbm_status lbm_fields(lbm_ctx* c, double* rho, double* u, double* T) {
     lbm_status st = enter(c);

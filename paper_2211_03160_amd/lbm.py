@@ -27,6 +27,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_INVALID", -2: "LBM_E_DEVICE",
 EXPORTS = ["lbm_derive", "lbm_workspace_bytes", "lbm_bytes_per_update",
            "lbm_create", "lbm_init", "lbm_init_fields", "lbm_step",
            "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
+           "lbm_set_debug_poison", "lbm_get_debug_poison",
            "lbm_fields", "lbm_nusselt", "lbm_wall_flux", "lbm_diagnostics",
            "lbm_state_bytes", "lbm_export_state", "lbm_import_state",
            "lbm_time", "lbm_destroy", "lbm_last_error", "lbm_lattice",
@@ -107,6 +108,9 @@ def lib():
         L.lbm_set_steps_per_launch.argtypes = [P, C.c_int32]
         L.lbm_get_steps_per_launch.argtypes = [P]
         L.lbm_get_steps_per_launch.restype = C.c_int32
+        L.lbm_set_debug_poison.argtypes = [P, C.c_int32]
+        L.lbm_get_debug_poison.argtypes = [P]
+        L.lbm_get_debug_poison.restype = C.c_int32
         L.lbm_fields.argtypes = [P, P, P, P]
         L.lbm_nusselt.argtypes = [P, dp, dp]
         L.lbm_wall_flux.argtypes = [P, dp, dp]
@@ -156,7 +160,7 @@ def lib():
                      "lbm_batch_get_config", "lbm_batch_set_steps_per_launch"):
             getattr(L, name).restype = C.c_int32
         for name in ("lbm_derive", "lbm_create", "lbm_init", "lbm_init_fields",
-                     "lbm_step", "lbm_set_steps_per_launch", "lbm_fields",
+                     "lbm_step", "lbm_set_steps_per_launch", "lbm_set_debug_poison", "lbm_fields",
                      "lbm_nusselt", "lbm_wall_flux",
                      "lbm_diagnostics", "lbm_export_state", "lbm_import_state",
                      "lbm_lattice"):
@@ -296,13 +300,23 @@ class Cavity:
 
     @property
     def steps_per_launch(self) -> int:
-        """Steps per kernel launch of step(): 1 .. 4 (above 1 in 2D only; a 2D
-        cavity starts with the fastest count for its storage mode)."""
+        """Steps per kernel launch of step(): 1 .. 5 in 2D, 1 or 2 in 3D; a
+        cavity starts with the fastest count for its storage mode."""
         return int(lib().lbm_get_steps_per_launch(self._h))
 
     @steps_per_launch.setter
     def steps_per_launch(self, k: int):
         self._check(lib().lbm_set_steps_per_launch(self._h, int(k)))
+
+    @property
+    def debug_poison(self) -> bool:
+        """Debug mode: the buffer each launch writes is filled with NaN
+        first, so a population left unwritten shows as non-finite."""
+        return bool(lib().lbm_get_debug_poison(self._h))
+
+    @debug_poison.setter
+    def debug_poison(self, on: bool):
+        self._check(lib().lbm_set_debug_poison(self._h, 1 if on else 0))
 
     @property
     def t(self) -> int:
@@ -444,7 +458,7 @@ class Batch:
 
     @property
     def steps_per_launch(self) -> int:
-        """Steps per launch of step(): 1, or 2..4 (streaming, 2D)."""
+        """Steps per launch of step(): 1, or 2..5 (streaming, 2D)."""
         return int(lib().lbm_batch_get_steps_per_launch(self._h))
 
     @steps_per_launch.setter
