@@ -18,13 +18,12 @@
 // step 2 on the 30 x 14 interior, which the block stores; tiles overlap by
 // two columns and two rows.  Every node update is step_node on the same
 // (storage-rounded) values as a one-step launch, so results are bitwise
-// those of single steps.  The loads of step 1 for plane p + 3 are issued
-// before step 2 of plane p and used one plane later, so they are in flight
-// for a whole iteration.  The
-// register ring rotates by moves and the LDS ring by a uniform slot
-// counter, so the plane loop holds one instance of each step; blocks whose
-// tile and z segment keep one node clear of every wall run a copy of the
-// loop without wall rules.
+// those of single steps.  The loads of step 1 for the next plane are
+// issued right after step 1 of this one and are in flight through the next
+// plane's step 2.  The register ring rotates by moves and the LDS ring by a
+// uniform slot counter, so the plane loop holds one instance of each step;
+// blocks whose tile and z segment keep one node clear of every wall run a
+// copy of the loop without wall rules.
 #pragma once
 
 namespace lbm {
@@ -181,10 +180,7 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
     constexpr int kSlot = kT3Cross * kT3Threads;  // elements of one LDS ring slot
 
     R rm[kT3Own] = {}, rz[kT3Own] = {}, rp[kT3Own] = {}, rn[kT3Own];  // register ring: planes p-1, p, p+1, new
-    // step-1 sources: two register sets, used alternately by the plane loop
-    // (unrolled twice), so the set gathered for the next iteration is never
-    // copied and stays in flight until that iteration reads it
-    R pfA[QF], pgA[QG], pfB[QF], pgB[QG];
+    R pf[QF], pg[QG];  // step-1 sources of the next plane, gathered ahead
 
     // the plane of step 1 for ring position q (relative to z0 - 1), wrapped
     // on a periodic z axis, -1 if it lies beyond a wall or is not needed.
@@ -271,52 +267,36 @@ __device__ __forceinline__ void stream3_segment(const Stream3Args<St>& a, typena
     for (int q = 0; q < 3; ++q) {
         const int32_t zq = step1_plane(q);
         if (!Walls || zq >= 0) {
-            gather(zq, pfA, pgA);
-            step1(zq, q, pfA, pgA);
+            gather(zq, pf, pg);
+            step1(zq, q, pf, pg);
         }
         rotate();
     }
     int32_t zn = step1_plane(3);
-    if (!Walls || zn >= 0) gather(zn, pfA, pgA);
+    if (!Walls || zn >= 0) gather(zn, pf, pg);
     __syncthreads();
     // Plane p = z0 + r needs ring positions r, r + 1, r + 2 (LDS slots s0,
     // s0 + 1, s0 + 2 mod 3 with s0 = r mod 3); then step 1 of position
     // r + 3 (plane p + 2, its sources gathered one iteration earlier) goes
-    // into slot s0, which step 2 has just read, while the sources of
-    // position r + 4 are loaded.  Loads and stores retire through one in-order counter (at most 63 in
-    // flight), and a store's data registers are read after it issues (so
-    // overwriting them waits for the store).  The order below keeps both
-    // waits short: the sources that step 1 of iteration r reads were
-    // gathered in iteration r - 1 into the other register set of two (no
-    // copy, so they stay in flight), and only this iteration's stores and
-    // gather are younger (52 operations); step 2 of iteration r + 1
-    // overwrites the store data of iteration r after step 1 has run.
+    // into slot s0, which step 2 has just read, and the sources of position
+    // r + 4 are loaded, to be used after the next plane's step 2.  (Keeping
+    // a second register set so that these loads could be issued before
+    // step 1 measured 7 % slower: more registers, no gain in latency.)
     int s0 = 0;
-    auto iteration = [&](int32_t r, const R (&cf)[QF], const R (&cg)[QG], R (&nf)[QF], R (&ng)[QG])
-                         __attribute__((always_inline)) {
+    const int32_t planes = z1 - z0;
+    for (int32_t r = 0; r < planes; ++r) {
         const int s1 = s0 == 2 ? 0 : s0 + 1, s2 = s1 == 2 ? 0 : s1 + 1;
         step2(z0 + r, s0, s1, s2, ef, eg);
         store2(z0 + r, ef, eg);
         __syncthreads();
+        if (!Walls || zn >= 0) step1(zn, s0, pf, pg);
         const int32_t zn2 = step1_plane(r + 4);
-        if (!Walls || zn2 >= 0) gather(zn2, nf, ng);  // read by step 1 of the next iteration
-        // keep the compiler from sinking those loads below step 1's
-        // arithmetic (which would leave them half an iteration instead of a
-        // whole one): nothing is scheduled across this point
-        __builtin_amdgcn_sched_barrier(0);
-        if (!Walls || zn >= 0) step1(zn, s0, cf, cg);
+        if (!Walls || zn2 >= 0) gather(zn2, pf, pg);
         rotate();
         zn = zn2;
         __syncthreads();
         s0 = s1;
-    };
-    const int32_t planes = z1 - z0;
-    int32_t r = 0;
-    for (; r + 1 < planes; r += 2) {
-        iteration(r, pfA, pgA, pfB, pgB);
-        iteration(r + 1, pfB, pgB, pfA, pgA);
     }
-    if (r < planes) iteration(r, pfA, pgA, pfB, pgB);
 }
 
 template <class St>
