@@ -388,9 +388,9 @@ def main():
         "rb2d_8193_fp16": (W.with_storage(cfg32, "fp16"), Wm, K),
         "rb2d_8193_bf16": (W.with_storage(cfg32, "bf16"), Wm, K),
         "rb2d_8193_mixed": (W.with_storage(cfg32, "mixed"), Wm, K),
-        "rb3d_385_fp32": (W.C2["cfg"], 6, W.C2["steps"]),
-        "rb3d_385_fp32_1": (W.C2["cfg"], 6, W.C2["steps"]),
-        "rb3d_385_fp64": (W.with_storage(W.C2["cfg"], "fp64"), 6, W.C2["steps"]),
+        "rb3d_385_fp32": (W.C2["cfg"], 5, W.C2["steps"]),
+        "rb3d_385_fp32_1": (W.C2["cfg"], 5, W.C2["steps"]),
+        "rb3d_385_fp64": (W.with_storage(W.C2["cfg"], "fp64"), 5, W.C2["steps"]),
         "rb3d_385_fp16": (W.with_storage(W.C2["cfg"], "fp16"), 5, W.C2["steps"]),
         "rb3d_385_bf16": (W.with_storage(W.C2["cfg"], "bf16"), 5, W.C2["steps"]),
         "rb3d_385_mixed": (W.with_storage(W.C2["cfg"], "mixed"), 5, W.C2["steps"]),
@@ -464,7 +464,7 @@ def main():
             variants[name] = r
             log(name, json.dumps(r))
         N3 = 385 ** 3
-        ref3 = run_case(cases["rb3d_385_fp64"][0], 6, W.C2["steps"], W.C2["seed"], W.C2["noise"])
+        ref3 = run_case(cases["rb3d_385_fp64"][0], 5, W.C2["steps"], W.C2["seed"], W.C2["noise"])
         ref3["roofline"] = hbm_roofline(ref3, N3, "lbm::step_kernel<3, StF64>", ceil["copy"]["gbs"])
         variants["rb3d_385_fp64"] = ref3
         log("rb3d_385_fp64", json.dumps(ref3))
