@@ -73,6 +73,26 @@ def test_config2_385_fp32_every_node_vs_oracle():
     _compare_full(c2["cfg"], 2, c2["seed"], c2["noise"])
 
 
+@pytest.mark.timeout(600)
+def test_config2_385_two_step_launches_bitwise():
+    """The 3D two-step kernel in the launch shape the bench times (z
+    segments sized for the whole GPU, wall-free and walled blocks): five
+    steps as two two-step launches and one single step against five
+    single steps, every byte of the state."""
+    c2 = W.C2
+    states = []
+    for spl in (2, 1):
+        g = lbm.Cavity(c2["cfg"])
+        g.steps_per_launch = spl
+        g.init(c2["seed"], c2["noise"])
+        g.step(5)
+        states.append(np.frombuffer(g.export_state(), np.uint8))
+        _log(f"385^3 FP32, {spl} step(s) per launch, t = {g.t}")
+        del g
+    bad = np.flatnonzero(states[0] != states[1])
+    assert bad.size == 0, f"{bad.size} bytes differ, first at {bad[:8]}"
+
+
 @pytest.mark.parametrize("cfg,steps", [(W.C1["cfg"], 300), (W.C2["cfg"], 200)])
 def test_full_size_mass_and_energy_budget(cfg, steps):
     """FP32 storage.  (16-bit deviations round at 2^-11 or 2^-8 per step,
