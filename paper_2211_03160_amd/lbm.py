@@ -269,10 +269,11 @@ class Cavity:
         _raise(lib().lbm_create(C.byref(self._p), C.c_void_p(self.workspace.data_ptr()),
                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
+        self._destroy = lib().lbm_destroy  # kept for close() at interpreter exit
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().lbm_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -422,11 +423,12 @@ class Batch:
         if st != 0:
             raise LBMError(st, lib().lbm_batch_last_error(None).decode())
         self._h = h
+        self._destroy = lib().lbm_batch_destroy  # kept for close() at interpreter exit
         self.nodes = [int(np.prod(list(c["n"]) + [1] * (3 - len(c["n"])))) for c in cfgs]
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().lbm_batch_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     def __del__(self):
