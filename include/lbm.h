@@ -17,7 +17,8 @@
  * wall rules, the moments, both collisions and the store of the
  * post-collision populations.  In 2D one kernel launch runs two to five
  * such steps (lbm_set_steps_per_launch), keeping the intermediate rows in
- * registers; in 3D one launch runs one or two.
+ * registers; in 3D one launch runs two (FP32 storage, the first step's
+ * planes in LDS and registers) or one.
  *
  * Conventions
  *   - Every function returns an lbm_status (or a documented value); none
@@ -173,9 +174,9 @@ lbm_status lbm_init(lbm_ctx* c, uint64_t seed, double amp);
 lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u,
                            const double* T);
 
-/* Enqueues n fused steps (n = 0: no-op; n < 0: LBM_E_INVALID).  In 2D
- * several steps go per launch (see lbm_set_steps_per_launch); a count that
- * does not divide n ends with shorter launches.                         */
+/* Enqueues n fused steps (n = 0: no-op; n < 0: LBM_E_INVALID).  Several
+ * steps go per launch (see lbm_set_steps_per_launch); a count that does
+ * not divide n ends with shorter launches.                              */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
 /* Steps per kernel launch of lbm_step: 1 .. 5 in 2D (5 with FP32 storage
