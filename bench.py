@@ -493,7 +493,7 @@ def main():
         log("sh2d_8193_fp32", json.dumps(sh))
 
         # learned warm start at 257^2: a 4-level, 32-base U-Net trained on
-        # about 2000 snapshots of Ra 1e5..1e8 cells, judged on 16 held-out
+        # about 2000 snapshots of Ra 1e5..1e8 cells, assessed on 16 held-out
         # cavities against independent plain runs (data, training and
         # evaluation all on the GPU, about 80 s)
         from paper_2211_03160_amd import warmstart as WS

@@ -6,9 +6,9 @@ developed convective state (T, u_x, u_y).  The lattice Boltzmann run then
 starts from that state (lbm_batch_init_fields) instead of from conduction
 plus noise.  Training data are snapshots of the developed flow produced by
 the solver itself (batched runs); the plain run from the conduction state
-is both the fallback and the judge.  Every held-out cavity runs three
+is both the fallback and the yardstick.  Every held-out cavity runs three
 times: plain, warm, and plain again with another noise seed (the reference,
-so that neither judged run is compared with its own record).  The
+so that neither assessed run is compared with its own record).  The
 evaluation counts the steps each start needs until the windowed mean of the
 wall Nusselt number stays inside a band around the reference's long-time
 mean (1%, wider for unsteady cells by their measured fluctuation), and the
@@ -220,7 +220,7 @@ def tail_stats(h, window, tail):
     return mean, sem, spread
 
 
-def judge(plain, warm, ref_run, every, window, tail):
+def assess(plain, warm, ref_run, every, window, tail):
     """Compare a plain and a warm run of one cavity with a third, independent
     plain run (another noise seed), the reference.  The reference's
     long-time mean is the target Nu.  The band around that target is 1%, or,
@@ -272,7 +272,7 @@ def evaluate(net, cfgs, seeds, ref_seeds, steps, every, levels, window):
     res = []
     for k in range(n):
         r = {"ra": cfgs[k]["ra"], "pr": cfgs[k]["pr"]}
-        r.update(judge(hist[:, k], hist[:, n + k], hist[:, 2 * n + k], every, window, tail))
+        r.update(assess(hist[:, k], hist[:, n + k], hist[:, 2 * n + k], every, window, tail))
         res.append(r)
     flags = b.unstable()
     return res, int(flags.sum()), hist

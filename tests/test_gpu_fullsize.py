@@ -96,7 +96,7 @@ def test_config2_385_two_step_launches_bitwise():
 @pytest.mark.parametrize("cfg,steps", [(W.C1["cfg"], 300), (W.C2["cfg"], 200)])
 def test_full_size_mass_and_energy_budget(cfg, steps):
     """FP32 storage.  (16-bit deviations round at 2^-11 or 2^-8 per step,
-    so mass is conserved only to that level; those forms are judged by
+    so mass is conserved only to that level; those forms are assessed by
     their Nusselt error against FP64 instead.)"""
     g = lbm.Cavity(cfg)
     g.init(1234, 1e-3)

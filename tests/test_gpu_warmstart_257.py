@@ -2,7 +2,7 @@
 unsteady), a 4-level U-Net with 32 base channels trained on about 2000
 snapshots the solver generates, then 16 held-out cavities run plain, warm
 and as an independent plain reference in one batch.  Unsteady cells are
-judged by a band sized from the reference's own fluctuation; the warm start
+assessed by a band sized from the reference's own fluctuation; the warm start
 must reach the developed state sooner (a bootstrap interval of the steps
 saved above zero), end as close to the reference's Nu as a second plain
 run does, and land in the reference's state as often.  (When a chaotic

@@ -1,5 +1,5 @@
 """Host-side logic of the warm-start evaluation on synthetic Nusselt records:
-the settling criterion, the judge against an independent reference run and
+the settling criterion, the assessment against an independent reference run and
 the bootstrap intervals.  No GPU is touched."""
 import math
 
@@ -24,12 +24,12 @@ def test_steps_to_steady_on_a_clean_exponential():
     assert WS.steps_to_steady(h[:w - 1], every, 1.0, w, tol) is None
 
 
-def test_judge_widens_the_band_for_a_fluctuating_reference():
+def test_assess_widens_the_band_for_a_fluctuating_reference():
     rng = np.random.default_rng(3)
     n, w, tail = 1200, 50, 360
     # steady cell: tiny noise, band stays at 1%
     ref = 4.0 + 1e-4 * rng.standard_normal(n)
-    r = WS.judge(ref.copy(), ref.copy(), ref, 100, w, tail)
+    r = WS.assess(ref.copy(), ref.copy(), ref, 100, w, tail)
     assert r["band"] == 0.01 and r["same_state_plain"] and r["steps_plain"] == w * 100
     # unsteady cell: red noise whose window means wander by several percent
     x = np.zeros(n)
@@ -37,12 +37,12 @@ def test_judge_widens_the_band_for_a_fluctuating_reference():
         x[k] = 0.98 * x[k - 1] + 0.05 * rng.standard_normal()
     ref = 10.0 + x
     _, sem, spread = WS.tail_stats(ref, w, tail)
-    r = WS.judge(np.roll(ref, 400), np.roll(ref, 800), ref, 100, w, tail)
+    r = WS.assess(np.roll(ref, 400), np.roll(ref, 800), ref, 100, w, tail)
     assert math.isclose(r["band"], max(0.01, 3 * math.hypot(spread, sem)))
     assert r["band"] > 0.01
 
 
-def test_judge_flags_another_state_and_a_faster_start():
+def test_assess_flags_another_state_and_a_faster_start():
     rng = np.random.default_rng(5)
     n, w, tail = 1000, 40, 300
     t = np.arange(n)
@@ -51,11 +51,11 @@ def test_judge_flags_another_state_and_a_faster_start():
     plain = 5.0 + 2.0 * np.exp(-t / 150.0) + noise()
     warm = 5.0 + 2.0 * np.exp(-t / 15.0) + noise()
     other = 4.0 + noise()  # a second roll state, 20% lower
-    r = WS.judge(plain, warm, ref, 500, w, tail)
+    r = WS.assess(plain, warm, ref, 500, w, tail)
     assert r["same_state_plain"] and r["same_state_warm"]
     assert r["steps_warm"] < r["steps_plain"]
     assert r["steps_warm_1pct"] is not None
-    r2 = WS.judge(plain, other, ref, 500, w, tail)
+    r2 = WS.assess(plain, other, ref, 500, w, tail)
     assert not r2["same_state_warm"] and r2["steps_warm"] is None
     assert abs(r2["nu_rel_err_warm"] - 0.2) < 0.01
     s = WS.summarize([dict(r, ra=1e5, pr=1.0), dict(r2, ra=1e6, pr=2.0)], n * 500, 0)
